@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the reactive colour-gradient lattice Boltzmann step on one MI355X.
+
+Workload: 128^3 porous mask (thresholded Gaussian random field, 512 plane waves of wavelength 16,
+seed 2, ~50% porosity), two colours on D3Q19 with the central-moment collision, surface tension
+0.01, Akai wetting at 60 degrees, body force 1e-6 along x on both colours, wall reaction xi = 1e-3,
+D3Q7 species with inlet C = 1 at x = 0, all-reactant start. FP32 populations (the headline), and
+FP16 / BF16 deviation storage with FP32 arithmetic; errors of each after the timed steps against
+an FP64 run of the same library. One step = one pass of the whole step over the lattice; the
+state is resident in HBM before the timed region starts.
+
+Prints one JSON line. value = million fluid-node updates per second (MFLUPS).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % HBM roofline, FP32 vs FP16-storage vs adjoint, at stated error"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+WORKLOAD = "bijel128"
+
+
+def bytes_per_fluid_update(precision):
+    """Algorithmic bytes per fluid node of each kernel (each array element moved once).
+
+    State per node: 19 colour-blind populations and 7 species populations in storage precision
+    (s bytes), 4 colour scalars (a, v) in arithmetic precision (r bytes); info word 4 bytes.
+    """
+    s = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[precision]
+    r = 8 if precision == "fp64" else 4
+    colour = 19 * s + 4 * r + 4 + r                  # pull f^m, (a, v); info; write rho^N
+    normal = r + 4 + 4 * r + 4 * r                   # rho^N; info; wetting data; write n*, |G|
+    collide = 26 * s + r + 4 * r + 4 + 26 * s + 4 * r  # pull f^m, g; rho^N; n*, |G|; info; write state
+    step_min = 2 * (26 * s + 4 * r) + 4              # state read once and written once, info
+    naive = 2 * 45 * s + 1                           # 45 per-colour populations in and out, flag byte
+    return dict(colour=colour, normal=normal, collide=collide, step_min=step_min, naive45=naive)
+
+
+def make_inputs(device):
+    from paper_2608_15781_amd import inputs
+
+    w, solid, theta, rr0, rp0 = inputs.workload_inputs(WORKLOAD, device=device)
+    return w, solid, theta, rr0, rp0
+
+
+def sim_kwargs(w):
+    return dict(tau=w["tau"], sigma=w["sigma"], beta=w["beta"], xi=w["xi"], accel=[(w["accel"], 0, 0)] * 2,
+                species=w["species"], x_open=w["x_open"], tau_species=w["tau_c"], c_inlet=w["c_in"])
+
+
+def run_mode(core, torch, w, solid, theta, rr0, rp0, precision, steps, warmup, profile):
+    sim = core.Lbm(w["shape"], solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision=precision,
+                   **sim_kwargs(w))
+    sim.step(warmup, reductions=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    red = sim.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern = None
+    if profile:
+        sim.set_profiling(True)
+        sim.step(steps, reductions=False)
+        ms, n = sim.kernel_times()
+        kern = {k: v / n for k, v in ms.items()}
+        sim.set_profiling(False)
+    return sim, red, dt, kern
+
+
+def rel_l2(a, b):
+    a = a.double()
+    b = b.double()
+    return float(((a - b).norm() / b.norm()).item()) if b.norm() > 0 else float((a - b).norm().item())
+
+
+def cpu_baseline(w, solid, theta, rr0, rp0, nfluid, steps):
+    import oracle
+
+    kw = dict(tau=w["tau"], sigma=w["sigma"], beta=w["beta"], accel=[(w["accel"], 0, 0)] * 2,
+              species=w["species"], x_open=w["x_open"], tau_c=w["tau_c"], c_in=w["c_in"])
+    o = oracle.Oracle(w["shape"], solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, xi=w["xi"], **kw)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return dict(value=nfluid * steps / dt / 1e6, unit="MFLUPS", cores=oracle.get_threads(), kind="oracle",
+                sample="%d steps of the full 128^3 workload (FP64, OpenMP over z), %.1f s" % (steps, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--modes", default="fp16,bf16", help="extra storage precisions to time")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (domain decomposition "
+              "across GPUs is described in the design notes but not implemented).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2608_15781_amd import core
+
+    core.lib()
+    print("bench: building %s inputs" % WORKLOAD, file=sys.stderr, flush=True)
+    w, solid, theta, rr0, rp0 = make_inputs("cuda:0")
+    nfluid = int((solid == 0).sum())
+    nx, ny, nz = w["shape"]
+    nall = nx * ny * nz
+
+    print("bench: fp32 headline, %d warmup + %d timed steps" % (args.warmup, args.steps), file=sys.stderr, flush=True)
+    sim32, red32, dt32, kern32 = run_mode(core, torch, w, solid, theta, rr0, rp0, "fp32", args.steps, args.warmup,
+                                          profile=True)
+    mflups = nfluid * args.steps / dt32 / 1e6
+    ms_step = dt32 * 1e3 / args.steps
+    b = bytes_per_fluid_update("fp32")
+    coll_s = kern32["collide"] * 1e-3
+    achieved = b["collide"] * nfluid / coll_s / 1e9
+
+    # Reference: the same steps in FP64 storage and arithmetic.
+    print("bench: fp64 reference run", file=sys.stderr, flush=True)
+    sim64, red64, dt64, _ = run_mode(core, torch, w, solid, theta, rr0, rp0, "fp64", args.steps, args.warmup,
+                                     profile=False)
+    m64 = sim64.moments()
+    conv64 = red64[:, 2].sum()
+
+    def errors(sim, red):
+        m = sim.moments()
+        rm = m["rho_r"] + m["rho_p"]
+        rm64 = m64["rho_r"] + m64["rho_p"]
+        return dict(rho_m=rel_l2(rm, rm64), u=rel_l2(m["u"], m64["u"]), rho_n=rel_l2(m["rho_n"], m64["rho_n"]),
+                    c=rel_l2(m["c"], m64["c"]), conversion=float(abs(red[:, 2].sum() - conv64) / conv64))
+
+    err32 = errors(sim32, red32)
+    modes = {"fp32": dict(mflups=mflups, ms_per_step=ms_step, error_vs_fp64=err32, kernel_ms=kern32),
+             "fp64": dict(mflups=nfluid * args.steps / dt64 / 1e6, ms_per_step=dt64 * 1e3 / args.steps)}
+    del sim32
+    for prec in [m for m in args.modes.split(",") if m]:
+        print("bench: %s mode" % prec, file=sys.stderr, flush=True)
+        sim, red, dt, kern = run_mode(core, torch, w, solid, theta, rr0, rp0, prec, args.steps, args.warmup,
+                                      profile=True)
+        bp = bytes_per_fluid_update(prec)
+        modes[prec] = dict(mflups=nfluid * args.steps / dt / 1e6, ms_per_step=dt * 1e3 / args.steps,
+                           error_vs_fp64=errors(sim, red), kernel_ms=kern,
+                           collide_gbs=bp["collide"] * nfluid / (kern["collide"] * 1e-3) / 1e9)
+        del sim
+    del sim64
+
+    cpu = None
+    if not args.no_cpu:
+        print("bench: cpu baseline (oracle, %d steps)" % args.cpu_steps, file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, solid, theta, rr0, rp0, nfluid, args.cpu_steps)
+
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "collide_bijel128_fp32_traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            t = json.load(f)
+        from paper_2608_15781_amd import build as lbm_build
+
+        if t.get("source_digest") == lbm_build.source_digest():
+            traffic = t.get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": round(mflups, 1),
+        "unit": "MFLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "128^3 porous GRF mask (wavelength 16, seed 2, porosity %.3f), D3Q19 two-colour "
+                               "CG-LBM + D3Q7 species, FP32 storage" % (nfluid / nall),
+                   "lattice": [nx, ny, nz], "fluid_nodes": nfluid, "parallelism": "single GPU"},
+        "mlups_all_nodes": round(nall * args.steps / dt32 / 1e6, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_collide",
+                     "alg_bytes_per_fluid_node": b["collide"], "avg_launch_ms": round(kern32["collide"], 5)},
+        "step_roofline": {"alg_bytes_per_fluid_update": b["step_min"],
+                          "frac": round(mflups * 1e6 * b["step_min"] / (HBM_PEAK_GBS * 1e9), 4),
+                          "naive45_bytes_per_fluid_update": b["naive45"],
+                          "naive45_equiv_frac": round(mflups * 1e6 * b["naive45"] / (HBM_PEAK_GBS * 1e9), 4)},
+        "modes": modes,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,164 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) reactive colour-gradient lattice Boltzmann step.
+ *
+ * Method: J.M.P. Beunen and J. Harting, "Gas-generating reactive flows in bicontinuous catalyst
+ * support structures". One call of lbm_step advances the two-colour D3Q19 colour-gradient model
+ * (Sec. II.A) by one time step per iteration: pull streaming with halfway bounce-back (eq.
+ * bounce_back) and periodic faces, the generalized central-moments collision (Appendix A, eqs.
+ * collision_operator .. back_transformation_vector), exact-difference forcing (eq.
+ * operator_perturbation) with the continuum-surface-force surface tension (eqs.
+ * continuum_surface_force, interface_curvature, color_gradient_normal, finite_difference_scheme),
+ * Latva-Kokko recolouring (eq. operator_recoloring), Akai wetting (eqs.
+ * color_lattice_weighted_average, realigned_normal_vectors, normal_vector_solid) and the
+ * first-order wall reaction that turns reactant (red) into product (gas) colour (eqs.
+ * nearest_solid_neighbors, reactive_boundary_condition_reactant/product). An optional D3Q7
+ * advection-diffusion species (not in the paper) is consumed by the same wall reaction.
+ *
+ * Conventions shared by every entry point:
+ *   - Node (x, y, z) has linear index n = x + nx*(y + ny*z); arrays of per-node vectors are
+ *     stored component-major: component a of node n at [a*N + n], N = nx*ny*nz.
+ *   - "Host" pointers are ordinary CPU memory, read during the call and not retained.
+ *     "Device" pointers are HIP device memory owned by the caller; the library borrows them
+ *     for the lifetime stated and never frees them.
+ *   - All work is ordered on the HIP stream given to lbm_init. Entry points that return host
+ *     data (reductions) synchronize that stream before returning.
+ *   - Real-valued device outputs use the context's real type: double when precision is
+ *     LBM_FP64, float otherwise.
+ *   - No call aborts or throws: every error is a negative lbm_status, with a message from
+ *     lbm_last_error(ctx). On an error the context's state is left as it was before the call
+ *     unless stated otherwise.
+ *   - Contact angles are in radians, measured through the red (reactant) colour.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_ARG = -1,         /* invalid argument (value, size, null pointer, too-small buffer) */
+  LBM_ERR_ALLOC = -2,       /* host allocation failed */
+  LBM_ERR_HIP = -3,         /* a HIP runtime call failed (message holds the HIP error string) */
+  LBM_ERR_NONFINITE = -4,   /* a step produced a non-finite value; state is kept for inspection */
+  LBM_ERR_STATE = -5,       /* call not valid in the context's current state */
+  LBM_ERR_UNSUPPORTED = -6  /* option combination not supported */
+} lbm_status;
+
+/* Storage precision of the populations. Arithmetic is FP64 for LBM_FP64 and FP32 otherwise;
+ * the five global reductions are always accumulated in FP64. The *_DEV modes store each
+ * population as its deviation from the lattice weight, scaled by 2^fp16_scale_log2 (FP16) or
+ * unscaled (BF16). */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_DEV = 2, LBM_BF16_DEV = 3 } lbm_precision;
+
+typedef struct lbm_ctx lbm_ctx; /* opaque */
+
+/* Problem statement (Sec. II and Sec. IV.B of the paper). */
+typedef struct {
+  int32_t nx, ny, nz;      /* lattice size, each >= 1, nx*ny*nz < 2^31 */
+  int32_t precision;       /* lbm_precision */
+  int32_t species;         /* 0: paper's model, reaction with C = 1; 1: D3Q7 species on */
+  int32_t x_open;          /* species only: inlet at x = 0 (C = c_inlet), outflow at x = nx-1 */
+  double tau;              /* relaxation time of the shear central moments, > 0.5 (eq. kinematic_viscosity) */
+  double tau_species;      /* species BGK relaxation time, > 0.5 (D = (tau_species - 1/2)/4) */
+  double sigma;            /* surface tension sigma >= 0 (eq. continuum_surface_force) */
+  double beta;             /* recolouring parameter beta >= 0 (eq. operator_recoloring) */
+  double xi;               /* reaction rate xi >= 0 (eq. reactive_boundary_condition_reactant) */
+  double accel[2][3];      /* body acceleration a^k of red (k = 0) and product (k = 1) */
+  double c_inlet;          /* species inlet concentration (x_open) */
+  double grad_eps;         /* colour gradients with |grad rho^N| <= grad_eps give n = 0; > 0 */
+  int32_t fp16_scale_log2; /* deviation scale exponent for LBM_FP16_DEV, 0..20 */
+  int32_t reserved;        /* must be 0 */
+} lbm_params;
+
+/* Level-t sums of one step (eqs. reactant_mass, product_mass, production_rate), in FP64:
+ * m^r = sum rho^r, m^p = sum rho^p, conversion = sum of converted red mass, species_total =
+ * sum C, nonfinite = number of fluid nodes with a non-finite result. */
+typedef struct {
+  double mass_r, mass_p, conversion, species_total, nonfinite;
+} lbm_reductions;
+
+/* Library version string (static storage). */
+const char* lbm_version(void);
+
+/* Bytes of device workspace that lbm_init needs for these parameters. */
+lbm_status lbm_workspace_bytes(const lbm_params* params, size_t* bytes);
+
+/* Bytes of one opaque state snapshot (lbm_get_state / lbm_set_state / lbm_adjoint_step). */
+lbm_status lbm_state_bytes(const lbm_params* params, size_t* bytes);
+
+/* Creates a context and writes the initial state S_0 = f^eq(rho^k_0, 0) per colour (and
+ * g = w C_0 for the species). Host inputs, N values each:
+ *   solid     uint8, 1 = solid node, 0 = fluid (required)
+ *   theta     double, contact angle in [0, pi] per node (read at wetting nodes); NULL = use
+ *             theta_uniform everywhere
+ *   reactive  uint8 r(x) (1 = reaction active); NULL = every fluid node with a solid face
+ *             neighbour (NN > 0)
+ *   rho_r0, rho_p0  double, initial colour densities (read at fluid nodes, rho_r0 + rho_p0 > 0)
+ *   c0        double initial species concentration; NULL = 1 (ignored without species)
+ * d_workspace: device memory of at least lbm_workspace_bytes, 256-byte aligned, owned by the
+ * caller and used by the context until lbm_free. stream: hipStream_t or NULL (default stream).
+ * Errors: LBM_ERR_ARG for invalid parameters or inputs (tau <= 0.5, negative sigma/beta/xi,
+ * theta outside [0, pi], non-finite values, non-positive mixture density at a fluid node,
+ * misaligned or too small workspace); LBM_ERR_HIP. *out is set only on success. */
+lbm_status lbm_init(const lbm_params* params, const uint8_t* solid, const double* theta, double theta_uniform,
+                    const uint8_t* reactive, const double* rho_r0, const double* rho_p0, const double* c0,
+                    void* d_workspace, size_t workspace_bytes, void* stream, lbm_ctx** out);
+
+/* Advances nsteps >= 0 time steps on the context's stream. per_step: host array of nsteps
+ * lbm_reductions (level t of each step) or NULL. Synchronizes the stream before returning.
+ * Returns LBM_ERR_NONFINITE if any step counted a non-finite node (the state after the
+ * last step is kept). */
+lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps, lbm_reductions* per_step);
+
+/* Level-t fields of the current state without changing it (steps up to the forcing of the
+ * next update): rho^r, rho^p, rho^N (N each), the physical velocity u + F/(2 rho^m)
+ * (3N, component-major) and the species concentration C (N; 1 without species). Device
+ * pointers of the context's real type; any may be NULL. Solid nodes receive 0. */
+lbm_status lbm_moments(lbm_ctx* ctx, void* d_rho_r, void* d_rho_p, void* d_rho_n, void* d_u, void* d_c);
+
+/* The post-collision populations S_t per colour, expanded from the internal representation:
+ * d_fr, d_fp (19N each, population-major [i*N + n], lattice order of the paper's matrix M with
+ * the rest vector last) and d_g (7N, order +x,-x,+y,-y,+z,-z,rest; may be NULL). Device
+ * pointers of the context's real type. Solid nodes receive 0. */
+lbm_status lbm_populations(lbm_ctx* ctx, void* d_fr, void* d_fp, void* d_g);
+
+/* Static geometry computed at init, for inspection: d_info (uint32 N) holds, at fluid nodes,
+ * bit i (i < 18) = node x - c_i is solid, bit 18 = fluid, bit 19 = wetting node (some
+ * neighbour solid), bits 20..22 = r(x) * NN(x); at solid nodes bit i (i < 18) = node x + c_i
+ * is fluid and bit 23 = colour is extrapolated into this node. d_wet (4N, real type): unit
+ * solid normal n_s (components 0..2, zero where undefined) and cos(theta) (component 3).
+ * Either may be NULL. */
+lbm_status lbm_geometry(lbm_ctx* ctx, void* d_info, void* d_wet);
+
+/* Copies the current state (lbm_state_bytes) to / from caller device memory, stream-ordered.
+ * Together with lbm_steps_done this is a bitwise-exact checkpoint. */
+lbm_status lbm_get_state(lbm_ctx* ctx, void* d_dst);
+lbm_status lbm_set_state(lbm_ctx* ctx, const void* d_src, int64_t steps_done);
+
+/* Kernel timing with HIP events recorded on the context's stream around each of the four
+ * launches of every step (colour, extrap, normal, collide) while enabled. Enabling resets the
+ * totals. lbm_kernel_times writes the accumulated device time in milliseconds of each of the
+ * four kernels (host array of 4) and the number of timed steps. Timing does not change results.
+ * Errors: LBM_ERR_HIP if an event cannot be created or queried. */
+lbm_status lbm_set_profiling(lbm_ctx* ctx, int32_t enable);
+lbm_status lbm_kernel_times(lbm_ctx* ctx, double* kernel_ms, int64_t* steps);
+
+/* Number of steps taken since init (or the value given to lbm_set_state). */
+int64_t lbm_steps_done(const lbm_ctx* ctx);
+
+/* Releases the context (host memory only; the workspace belongs to the caller). */
+void lbm_free(lbm_ctx* ctx);
+
+/* Message of the last error on this context (static or context-owned storage; never NULL). */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

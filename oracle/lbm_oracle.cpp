@@ -211,8 +211,12 @@ void cm_back_transform(const T& ux, const T& uy, const T& uz, const T k[5], T d[
 }
 
 // Akai wetting, eq. (realigned_normal_vectors): both candidates n+ and n-, then the one with the
-// smaller Euclidean distance to n (ties keep n+). theta' = arccos(n_s . n). When sin(theta')
-// vanishes (n parallel to n_s) the candidates are undefined and n is kept.
+// smaller Euclidean distance to n (ties keep n+). theta' = arccos(n_s . n). The candidates divide
+// by sin(theta') and are undefined when n is parallel to n_s (no plane to rotate in); n is kept
+// whenever sin(theta') <= kAkaiSinMin, a bound far above rounding noise, so that the choice never
+// depends on the rounding of a near-zero perpendicular component.
+constexpr double kAkaiSinMin = 1e-6;
+
 template <class T>
 void wetting_realign(const T n[3], const double ns[3], const T& theta, T out[3], T np[3], T nm[3]) {
   T dot = n[0] * ns[0] + n[1] * ns[1] + n[2] * ns[2];
@@ -221,7 +225,7 @@ void wetting_realign(const T n[3], const double ns[3], const T& theta, T out[3],
   T thp = acos(dot);
   T sthp = sin(thp);
   for (int a = 0; a < 3; ++a) { out[a] = n[a]; np[a] = n[a]; nm[a] = n[a]; }
-  if (!(val(sthp) > 1e-12)) return;
+  if (!(val(sthp) > kAkaiSinMin)) return;
   T cthp = cos(thp);
   T cp = cos(theta), sp = sin(theta);          // cos(+theta), sin(+theta)
   T cm = cos(-1.0 * theta), sm = sin(-1.0 * theta);  // cos(-theta), sin(-theta)

@@ -1,0 +1,242 @@
+"""ctypes binding of liblbm.so. Argument marshalling only: every step of the method runs in the
+library's HIP kernels; torch provides the device memory and the stream.
+
+The library must have been built (``python -m paper_2608_15781_amd.build``); loading raises if it
+is missing, and there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from . import build as _build
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+LBM_OK, LBM_ERR_ARG, LBM_ERR_ALLOC, LBM_ERR_HIP, LBM_ERR_NONFINITE, LBM_ERR_STATE, LBM_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+EXPORTED = ["lbm_version", "lbm_workspace_bytes", "lbm_state_bytes", "lbm_init", "lbm_step", "lbm_moments",
+            "lbm_populations", "lbm_geometry", "lbm_get_state", "lbm_set_state", "lbm_set_profiling",
+            "lbm_kernel_times", "lbm_steps_done", "lbm_free", "lbm_last_error"]
+KERNELS = ("colour", "extrap", "normal", "collide")
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("lbm status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("species", ctypes.c_int32), ("x_open", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("tau_species", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("beta", ctypes.c_double), ("xi", ctypes.c_double), ("accel", (ctypes.c_double * 3) * 2),
+        ("c_inlet", ctypes.c_double), ("grad_eps", ctypes.c_double), ("fp16_scale_log2", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Reductions(ctypes.Structure):
+    _fields_ = [("mass_r", ctypes.c_double), ("mass_p", ctypes.c_double), ("conversion", ctypes.c_double),
+                ("species_total", ctypes.c_double), ("nonfinite", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads liblbm.so from the package directory; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            raise RuntimeError("liblbm.so is not built: run `python -m paper_2608_15781_amd.build` "
+                               "(or __graft_entry__.build())")
+        L = ctypes.CDLL(_build.LIB)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        P = ctypes.POINTER
+        L.lbm_version.restype = ctypes.c_char_p
+        L.lbm_workspace_bytes.argtypes = [P(Params), P(sz)]
+        L.lbm_state_bytes.argtypes = [P(Params), P(sz)]
+        L.lbm_init.argtypes = [P(Params), vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, sz, vp, P(vp)]
+        L.lbm_step.argtypes = [vp, i32, vp]
+        L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.lbm_populations.argtypes = [vp, vp, vp, vp]
+        L.lbm_geometry.argtypes = [vp, vp, vp]
+        L.lbm_get_state.argtypes = [vp, vp]
+        L.lbm_set_state.argtypes = [vp, vp, i64]
+        L.lbm_set_profiling.argtypes = [vp, i32]
+        L.lbm_kernel_times.argtypes = [vp, vp, vp]
+        L.lbm_steps_done.argtypes = [vp]
+        L.lbm_steps_done.restype = i64
+        L.lbm_free.argtypes = [vp]
+        L.lbm_last_error.argtypes = [vp]
+        L.lbm_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("lbm_version", "lbm_steps_done", "lbm_free", "lbm_last_error"):
+                getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def make_params(shape, precision="fp32", tau=1.0, tau_species=0.9, sigma=0.0, beta=0.7, xi=0.0,
+                accel=((0, 0, 0), (0, 0, 0)), species=False, x_open=False, c_inlet=1.0, grad_eps=1e-6,
+                fp16_scale_log2=12) -> Params:
+    p = Params()
+    p.nx, p.ny, p.nz = (int(s) for s in shape)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.species, p.x_open = int(bool(species)), int(bool(x_open))
+    p.tau, p.tau_species, p.sigma, p.beta, p.xi = tau, tau_species, sigma, beta, xi
+    for k in range(2):
+        for a in range(3):
+            p.accel[k][a] = float(accel[k][a])
+    p.c_inlet, p.grad_eps, p.fp16_scale_log2, p.reserved = c_inlet, grad_eps, fp16_scale_log2, 0
+    return p
+
+
+def _host(a, dtype, n):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if a.size == 1 and n != 1:
+        a = np.full(n, a.reshape(()), dtype=dtype)
+    if a.size != n:
+        raise ValueError("expected %d values, got %d" % (n, a.size))
+    return a.reshape(n)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Lbm:
+    """One simulation context on one GPU.
+
+    shape = (nx, ny, nz); per-node inputs are arrays of shape (nz, ny, nx) (x fastest) or flat.
+    Keyword parameters map one to one onto lbm_params (see include/lbm.h).
+    """
+
+    def __init__(self, shape, solid=None, theta=None, theta_uniform=math.pi / 2, reactive=None, rho_r0=1.0,
+                 rho_p0=0.0, c0=None, device="cuda:0", stream=None, **kw):
+        import torch
+
+        self.torch = torch
+        self.shape = tuple(int(s) for s in shape)
+        nx, ny, nz = self.shape
+        self.N = nx * ny * nz
+        self.params = make_params(self.shape, **kw)
+        self.precision = self.params.precision
+        self.real = torch.float64 if self.precision == 0 else torch.float32
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L = lib()
+        ws = ctypes.c_size_t()
+        self._check(L.lbm_workspace_bytes(ctypes.byref(self.params), ctypes.byref(ws)), None)
+        sb = ctypes.c_size_t()
+        self._check(L.lbm_state_bytes(ctypes.byref(self.params), ctypes.byref(sb)), None)
+        self.workspace_bytes, self.state_bytes = ws.value, sb.value
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._ws_ptr = base + off
+        N = self.N
+        solid = np.zeros(N, np.uint8) if solid is None else _host(solid, np.uint8, N)
+        th = _host(theta, np.float64, N)
+        react = _host(reactive, np.uint8, N)
+        rr, rp = _host(rho_r0, np.float64, N), _host(rho_p0, np.float64, N)
+        c0a = _host(c0, np.float64, N)
+        self.solid = solid
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = L.lbm_init(ctypes.byref(self.params), _p(solid), _p(th), float(theta_uniform), _p(react), _p(rr),
+                            _p(rp), _p(c0a), ctypes.c_void_p(self._ws_ptr), self.workspace_bytes,
+                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        self._check(st, None)
+        self._h = h
+
+    def _check(self, status, h):
+        if status != LBM_OK:
+            msg = lib().lbm_last_error(h).decode()
+            raise LbmError(status, msg)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().lbm_free(h)
+            self._h = None
+
+    close = __del__
+
+    @property
+    def steps_done(self) -> int:
+        return int(lib().lbm_steps_done(self._h))
+
+    def step(self, nsteps=1, reductions=True, check=True):
+        """Advance nsteps; returns an (nsteps, 5) array [mass_r, mass_p, conversion, species, nonfinite]."""
+        out = (Reductions * max(1, nsteps))() if reductions else None
+        st = lib().lbm_step(self._h, int(nsteps), out)
+        if check:
+            self._check(st, self._h)
+        self.last_status = st
+        if not reductions:
+            return None
+        return np.frombuffer(out, dtype=np.float64).reshape(-1, 5)[:nsteps].copy()
+
+    def _grid(self, t, comps=1):
+        nx, ny, nz = self.shape
+        return t.view(comps, nz, ny, nx) if comps > 1 else t.view(nz, ny, nx)
+
+    def moments(self):
+        """Level-t fields as device tensors of shape (nz, ny, nx) ((3, nz, ny, nx) for u)."""
+        t = self.torch
+        N = self.N
+        rr, rp, rn, c = (t.empty(N, dtype=self.real, device=self.device) for _ in range(4))
+        u = t.empty(3 * N, dtype=self.real, device=self.device)
+        self._check(lib().lbm_moments(self._h, rr.data_ptr(), rp.data_ptr(), rn.data_ptr(), u.data_ptr(),
+                                      c.data_ptr()), self._h)
+        self.stream.synchronize()
+        return dict(rho_r=self._grid(rr), rho_p=self._grid(rp), rho_n=self._grid(rn), u=self._grid(u, 3),
+                    c=self._grid(c))
+
+    def populations(self):
+        """Post-collision populations per colour, (19, N), (19, N), (7, N) device tensors."""
+        t = self.torch
+        N = self.N
+        fr = t.empty(19 * N, dtype=self.real, device=self.device)
+        fp = t.empty(19 * N, dtype=self.real, device=self.device)
+        g = t.empty(7 * N, dtype=self.real, device=self.device)
+        self._check(lib().lbm_populations(self._h, fr.data_ptr(), fp.data_ptr(), g.data_ptr()), self._h)
+        self.stream.synchronize()
+        return fr.view(19, N), fp.view(19, N), g.view(7, N)
+
+    def geometry(self):
+        t = self.torch
+        info = t.empty(self.N, dtype=t.int32, device=self.device)
+        wet = t.empty(4 * self.N, dtype=self.real, device=self.device)
+        self._check(lib().lbm_geometry(self._h, info.data_ptr(), wet.data_ptr()), self._h)
+        self.stream.synchronize()
+        return info, wet.view(4, self.N)
+
+    def get_state(self):
+        buf = self.torch.empty(self.state_bytes, dtype=self.torch.uint8, device=self.device)
+        self._check(lib().lbm_get_state(self._h, buf.data_ptr()), self._h)
+        self.stream.synchronize()
+        return buf
+
+    def set_profiling(self, enable: bool):
+        self._check(lib().lbm_set_profiling(self._h, int(bool(enable))), self._h)
+
+    def kernel_times(self):
+        """Accumulated device milliseconds per kernel and the number of timed steps."""
+        ms = (ctypes.c_double * 4)()
+        n = ctypes.c_int64()
+        self._check(lib().lbm_kernel_times(self._h, ms, ctypes.byref(n)), self._h)
+        return dict(zip(KERNELS, list(ms))), int(n.value)
+
+    def set_state(self, buf, steps_done):
+        if buf.numel() != self.state_bytes or buf.device != self.device:
+            raise ValueError("state buffer must hold %d bytes on %s" % (self.state_bytes, self.device))
+        self._check(lib().lbm_set_state(self._h, buf.data_ptr(), int(steps_done)), self._h)
+        self.stream.synchronize()

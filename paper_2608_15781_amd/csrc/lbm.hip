@@ -1,0 +1,572 @@
+// C ABI of the MI355X reactive colour-gradient lattice Boltzmann step: context, workspace
+// layout, initialisation kernels and launch sequences. The per-step kernels live in
+// step_kernels.hpp. Build: hipcc --offload-arch=gfx950 (see the package's build module).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbm.h"
+#include "lattice.hpp"
+#include "precision.hpp"
+#include "step_kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int kRing = 1024;          // per-step reduction rows kept on the device
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+size_t store_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2); }
+size_t real_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
+
+struct Layout {
+  size_t info, wet, rhoN, nst, state[2], partials, counter, ring, total;
+  size_t f_off, a_off, g_off, state_bytes;  // within one state buffer
+  int nblocks;
+};
+
+Layout make_layout(const lbm_params& p) {
+  Layout L{};
+  const size_t N = size_t(p.nx) * p.ny * p.nz;
+  const size_t s = store_bytes(p.precision), r = real_bytes(p.precision);
+  L.f_off = 0;
+  L.a_off = align_up(19 * s * N);
+  L.g_off = align_up(L.a_off + 4 * r * N);
+  L.state_bytes = align_up(L.g_off + (p.species ? 7 * s * N : 0));
+  int nb = int((N + kBlock - 1) / kBlock);
+  nb = (nb + kXcd - 1) / kXcd * kXcd;
+  L.nblocks = nb;
+  size_t o = 0;
+  L.info = o; o = align_up(o + 4 * N);
+  L.wet = o; o = align_up(o + 4 * r * N);
+  L.rhoN = o; o = align_up(o + r * N);
+  L.nst = o; o = align_up(o + 4 * r * N);
+  L.state[0] = o; o = align_up(o + L.state_bytes);
+  L.state[1] = o; o = align_up(o + L.state_bytes);
+  L.partials = o; o = align_up(o + 5 * sizeof(double) * size_t(nb));
+  L.counter = o; o = align_up(o + sizeof(unsigned));
+  L.ring = o; o = align_up(o + 5 * sizeof(double) * kRing);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  int N;
+  Layout L;
+  char* ws;
+  hipStream_t stream;
+  int cur;  // index of the state buffer holding S_t
+  int64_t steps;
+  char err[512];
+  // Profiling: 5 events per step of the current chunk (before colour, after each kernel).
+  bool prof;
+  std::vector<hipEvent_t> ev;
+  double kernel_ms[4];
+  int64_t prof_steps;
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
+  if (c) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+  }
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail((ctx), LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+char g_err[512] = "";
+
+lbm_status check_params(const lbm_params* p, char* msg, size_t len) {
+  if (!p) { snprintf(msg, len, "params is NULL"); return LBM_ERR_ARG; }
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) { snprintf(msg, len, "lattice size must be >= 1"); return LBM_ERR_ARG; }
+  const double N = double(p->nx) * p->ny * p->nz;
+  if (N >= 2147483647.0) { snprintf(msg, len, "nx*ny*nz must be < 2^31"); return LBM_ERR_ARG; }
+  if (p->precision < LBM_FP64 || p->precision > LBM_BF16_DEV) { snprintf(msg, len, "unknown precision %d", p->precision); return LBM_ERR_ARG; }
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) { snprintf(msg, len, "tau must be finite and > 0.5"); return LBM_ERR_ARG; }
+  if (p->species && (!(p->tau_species > 0.5) || !std::isfinite(p->tau_species))) { snprintf(msg, len, "tau_species must be finite and > 0.5"); return LBM_ERR_ARG; }
+  if (!(p->sigma >= 0) || !std::isfinite(p->sigma)) { snprintf(msg, len, "sigma must be finite and >= 0"); return LBM_ERR_ARG; }
+  if (!(p->beta >= 0) || !std::isfinite(p->beta)) { snprintf(msg, len, "beta must be finite and >= 0"); return LBM_ERR_ARG; }
+  if (!(p->xi >= 0) || !std::isfinite(p->xi)) { snprintf(msg, len, "xi must be finite and >= 0"); return LBM_ERR_ARG; }
+  if (!(p->grad_eps > 0) || !std::isfinite(p->grad_eps)) { snprintf(msg, len, "grad_eps must be finite and > 0"); return LBM_ERR_ARG; }
+  for (int k = 0; k < 2; ++k)
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(p->accel[k][a])) { snprintf(msg, len, "accel must be finite"); return LBM_ERR_ARG; }
+  if (p->species && p->x_open && (!std::isfinite(p->c_inlet) || p->c_inlet < 0)) { snprintf(msg, len, "c_inlet must be finite and >= 0"); return LBM_ERR_ARG; }
+  if (p->precision == LBM_FP16_DEV && (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 20)) { snprintf(msg, len, "fp16_scale_log2 must be in 0..20"); return LBM_ERR_ARG; }
+  if (p->reserved != 0) { snprintf(msg, len, "reserved must be 0"); return LBM_ERR_ARG; }
+  if (p->species != 0 && p->species != 1) { snprintf(msg, len, "species must be 0 or 1"); return LBM_ERR_ARG; }
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Initialisation kernels
+// ------------------------------------------------------------------------------------------
+
+__device__ inline int wrap(int v, int n) { v %= n; return v < 0 ? v + n : v; }
+
+// Flags, bounce-back links, NN(x) (eq. nearest_solid_neighbors), wetting set, r(x) NN(x).
+__global__ void k_init_info(int nx, int ny, int nz, const uint8_t* solid, const uint8_t* reactive, int open,
+                            uint32_t* info) {
+  using D = D3Q19;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = nx * ny * nz;
+  if (n >= N) return;
+  const int x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
+  auto at = [&](int dx, int dy, int dz) { return wrap(x + dx, nx) + nx * (wrap(y + dy, ny) + ny * wrap(z + dz, nz)); };
+  uint32_t v = 0;
+  if (solid[n]) {
+    for (int i = 0; i < 18; ++i)
+      if (!solid[at(D::cx[i], D::cy[i], D::cz[i])]) v |= (1u << i);
+    if (v) v |= kExtrap;
+  } else {
+    int nn = 0;
+    for (int i = 0; i < 18; ++i) {
+      if (solid[at(-D::cx[i], -D::cy[i], -D::cz[i])]) v |= (1u << i);
+      if (i < 6 && solid[at(D::cx[i], D::cy[i], D::cz[i])]) ++nn;
+    }
+    v |= kFluid;
+    if (v & kLinkMask) v |= kWet;
+    const bool r = reactive ? (reactive[n] != 0) : (nn > 0);
+    if (r) v |= uint32_t(nn) << kRnnShift;
+    if (open && x == 0) v |= kInlet;
+    if (open && x == nx - 1) v |= kOutlet;
+  }
+  info[n] = v;
+}
+
+// Solid normal n_s at wetting nodes (eq. normal_vector_solid) over the 92-vector eighth-order
+// stencil. The weights of eq. (eigth_order_weight_function) are multiples of 1/5040, so the
+// sum is accumulated exactly in integers (5040 w = 448, 240, 96, 50, 16, 8, 1) and normalised
+// once; a zero sum leaves n_s undefined (stored as 0). Also stores cos(theta).
+template <class R>
+__global__ void k_init_wet(int nx, int ny, int nz, const uint8_t* solid, const uint32_t* info, const double* theta,
+                           double theta_uniform, R* wet) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = nx * ny * nz;
+  if (n >= N) return;
+  const int x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
+  const double th = theta ? theta[n] : theta_uniform;
+  long sx = 0, sy = 0, sz = 0;
+  if (info[n] & kWet) {
+    for (int ez = -2; ez <= 2; ++ez)
+      for (int ey = -2; ey <= 2; ++ey)
+        for (int ex = -2; ex <= 2; ++ex) {
+          const int e2 = ex * ex + ey * ey + ez * ez;
+          int w = 0;
+          switch (e2) {
+            case 1: w = 448; break;
+            case 2: w = 240; break;
+            case 3: w = 96; break;
+            case 4: w = 50; break;
+            case 5: w = 16; break;
+            case 6: w = 8; break;
+            case 8: w = 1; break;
+            default: w = 0;
+          }
+          if (w && solid[wrap(x + ex, nx) + nx * (wrap(y + ey, ny) + ny * wrap(z + ez, nz))]) {
+            sx += w * ex; sy += w * ey; sz += w * ez;
+          }
+        }
+  }
+  double len = sqrt(double(sx * sx + sy * sy + sz * sz));
+  double il = len > 0 ? 1.0 / len : 0.0;
+  wet[n] = R(sx * il);
+  wet[N + n] = R(sy * il);
+  wet[2 * N + n] = R(sz * il);
+  wet[3 * N + n] = R(cos(th));
+}
+
+// S_0 = f^eq(rho^k_0, 0) per colour: f^m = w (rho^r + rho^p), a = rho^r / rho^m, v = 0, g = w C_0.
+template <int P>
+__global__ void k_init_state(StepArgs<P> A, const double* rr0, const double* rp0, const double* c0) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= A.N) return;
+  const size_t N = A.N;
+  const bool fluid = A.info[n] & kFluid;
+  const double rm = fluid ? rr0[n] + rp0[n] : 1.0;
+  for (int i = 0; i < 19; ++i) A.fout[size_t(i) * N + n] = Prec<P>::st(R(D::w(i) * rm), R(D::w(i)), A.scale);
+  A.aout[n] = fluid ? R(rr0[n] / rm) : R(0);
+  A.aout[N + n] = 0;
+  A.aout[2 * N + n] = 0;
+  A.aout[3 * N + n] = 0;
+  if (A.species) {
+    const double c = c0 ? c0[n] : 1.0;
+    for (int i = 0; i < 7; ++i) A.gout[size_t(i) * N + n] = Prec<P>::st(R(D3Q7::w(i) * c), R(D3Q7::w(i)), A.gscale);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Launch helpers
+// ------------------------------------------------------------------------------------------
+
+template <int P>
+StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
+  using S = typename Prec<P>::S;
+  using R = typename Prec<P>::R;
+  StepArgs<P> A{};
+  const lbm_params& p = c->p;
+  const Layout& L = c->L;
+  A.nx = p.nx; A.ny = p.ny; A.nz = p.nz; A.N = c->N;
+  A.info = reinterpret_cast<const uint32_t*>(c->ws + L.info);
+  char* sb = c->ws + L.state[src_buf];
+  char* db = c->ws + L.state[1 - src_buf];
+  A.fin = reinterpret_cast<const S*>(sb + L.f_off);
+  A.ain = reinterpret_cast<const R*>(sb + L.a_off);
+  A.gin = reinterpret_cast<const S*>(sb + L.g_off);
+  A.fout = reinterpret_cast<S*>(db + L.f_off);
+  A.aout = reinterpret_cast<R*>(db + L.a_off);
+  A.gout = reinterpret_cast<S*>(db + L.g_off);
+  A.rhoN = reinterpret_cast<R*>(c->ws + L.rhoN);
+  A.nst = reinterpret_cast<R*>(c->ws + L.nst);
+  A.wet = reinterpret_cast<const R*>(c->ws + L.wet);
+  A.partials = reinterpret_cast<double*>(c->ws + L.partials);
+  A.counter = reinterpret_cast<unsigned*>(c->ws + L.counter);
+  A.ring_row = reinterpret_cast<double*>(c->ws + L.ring);
+  A.relax = R(1.0 - 1.0 / p.tau);
+  A.inv_tau_c = p.species ? R(1.0 / p.tau_species) : R(1);
+  A.sigma = R(p.sigma); A.beta = R(p.beta); A.xi = R(p.xi); A.c_in = R(p.c_inlet); A.eps = R(p.grad_eps);
+  for (int k = 0; k < 2; ++k)
+    for (int a = 0; a < 3; ++a) A.acc[k][a] = R(p.accel[k][a]);
+  const int k2 = p.precision == LBM_FP16_DEV ? p.fp16_scale_log2 : 0;
+  A.scale = R(std::ldexp(1.0, k2));
+  A.inv_scale = R(std::ldexp(1.0, -k2));
+  A.gscale = A.scale;
+  A.inv_gscale = A.inv_scale;
+  A.species = p.species;
+  return A;
+}
+
+template <int P>
+lbm_status launch_step(lbm_ctx* c, int slot) {
+  StepArgs<P> A = make_args<P>(c, c->cur);
+  A.ring_row = reinterpret_cast<double*>(c->ws + c->L.ring) + 5 * size_t(slot);
+  const dim3 grid(c->L.nblocks), block(kBlock);
+  hipEvent_t* ev = c->prof ? &c->ev[5 * size_t(slot)] : nullptr;
+  if (ev) HIP_TRY(c, hipEventRecord(ev[0], c->stream));
+  hipLaunchKernelGGL(k_colour<P>, grid, block, 0, c->stream, A);
+  if (ev) HIP_TRY(c, hipEventRecord(ev[1], c->stream));
+  hipLaunchKernelGGL(k_extrap<P>, grid, block, 0, c->stream, A);
+  if (ev) HIP_TRY(c, hipEventRecord(ev[2], c->stream));
+  hipLaunchKernelGGL(k_normal<P>, grid, block, 0, c->stream, A);
+  if (ev) HIP_TRY(c, hipEventRecord(ev[3], c->stream));
+  hipLaunchKernelGGL((k_collide<P, false>), grid, block, 0, c->stream, A);
+  if (ev) HIP_TRY(c, hipEventRecord(ev[4], c->stream));
+  HIP_TRY(c, hipGetLastError());
+  c->cur = 1 - c->cur;
+  c->steps++;
+  return LBM_OK;
+}
+
+template <int P>
+lbm_status launch_moments(lbm_ctx* c, void* rr, void* rp, void* rn, void* u, void* cc) {
+  using R = typename Prec<P>::R;
+  StepArgs<P> A = make_args<P>(c, c->cur);
+  A.m_rr = static_cast<R*>(rr); A.m_rp = static_cast<R*>(rp); A.m_rn = static_cast<R*>(rn);
+  A.m_u = static_cast<R*>(u); A.m_c = static_cast<R*>(cc);
+  const size_t N = c->N;
+  const size_t rb = sizeof(R);
+  for (void* ptr : {rr, rp, rn, cc})
+    if (ptr) HIP_TRY(c, hipMemsetAsync(ptr, 0, rb * N, c->stream));
+  if (u) HIP_TRY(c, hipMemsetAsync(u, 0, 3 * rb * N, c->stream));
+  const dim3 grid(c->L.nblocks), block(kBlock);
+  hipLaunchKernelGGL(k_colour<P>, grid, block, 0, c->stream, A);
+  hipLaunchKernelGGL(k_extrap<P>, grid, block, 0, c->stream, A);
+  hipLaunchKernelGGL(k_normal<P>, grid, block, 0, c->stream, A);
+  hipLaunchKernelGGL((k_collide<P, true>), grid, block, 0, c->stream, A);
+  HIP_TRY(c, hipGetLastError());
+  return LBM_OK;
+}
+
+template <int P>
+lbm_status launch_expand(lbm_ctx* c, void* fr, void* fp, void* g) {
+  using R = typename Prec<P>::R;
+  StepArgs<P> A = make_args<P>(c, c->cur);
+  const dim3 grid(c->L.nblocks), block(kBlock);
+  hipLaunchKernelGGL(k_expand<P>, grid, block, 0, c->stream, A, static_cast<R*>(fr), static_cast<R*>(fp),
+                     static_cast<R*>(g));
+  HIP_TRY(c, hipGetLastError());
+  return LBM_OK;
+}
+
+template <int P>
+lbm_status launch_init(lbm_ctx* c, const uint8_t* d_solid, const uint8_t* d_react, const double* d_theta,
+                       double theta_uniform, const double* d_rr, const double* d_rp, const double* d_c0) {
+  using R = typename Prec<P>::R;
+  const lbm_params& p = c->p;
+  const int tb = 256, gb = (c->N + tb - 1) / tb;
+  uint32_t* info = reinterpret_cast<uint32_t*>(c->ws + c->L.info);
+  hipLaunchKernelGGL(k_init_info, dim3(gb), dim3(tb), 0, c->stream, p.nx, p.ny, p.nz, d_solid, d_react,
+                     int(p.species && p.x_open), info);
+  hipLaunchKernelGGL(k_init_wet<R>, dim3(gb), dim3(tb), 0, c->stream, p.nx, p.ny, p.nz, d_solid, info, d_theta,
+                     theta_uniform, reinterpret_cast<R*>(c->ws + c->L.wet));
+  // The initial state goes into buffer 0 (make_args with src 1 writes buffer 0).
+  StepArgs<P> A = make_args<P>(c, 1);
+  hipLaunchKernelGGL(k_init_state<P>, dim3(gb), dim3(tb), 0, c->stream, A, d_rr, d_rp, d_c0);
+  HIP_TRY(c, hipGetLastError());
+  c->cur = 0;
+  return LBM_OK;
+}
+
+#define DISPATCH(ctx, fn, ...)                                   \
+  switch ((ctx)->p.precision) {                                  \
+    case LBM_FP64: return fn<0>((ctx), __VA_ARGS__);             \
+    case LBM_FP32: return fn<1>((ctx), __VA_ARGS__);             \
+    case LBM_FP16_DEV: return fn<2>((ctx), __VA_ARGS__);         \
+    default: return fn<3>((ctx), __VA_ARGS__);                   \
+  }
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_version(void) { return "lbm-mi355x 0.1 (gfx950)"; }
+
+lbm_status lbm_workspace_bytes(const lbm_params* params, size_t* bytes) {
+  lbm_status s = check_params(params, g_err, sizeof(g_err));
+  if (s != LBM_OK) return s;
+  if (!bytes) return LBM_ERR_ARG;
+  *bytes = make_layout(*params).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_state_bytes(const lbm_params* params, size_t* bytes) {
+  lbm_status s = check_params(params, g_err, sizeof(g_err));
+  if (s != LBM_OK) return s;
+  if (!bytes) return LBM_ERR_ARG;
+  *bytes = make_layout(*params).state_bytes;
+  return LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_params* params, const uint8_t* solid, const double* theta, double theta_uniform,
+                    const uint8_t* reactive, const double* rho_r0, const double* rho_p0, const double* c0,
+                    void* d_workspace, size_t workspace_bytes, void* stream, lbm_ctx** out) {
+  lbm_status s = check_params(params, g_err, sizeof(g_err));
+  if (s != LBM_OK) return s;
+  if (!out || !solid || !rho_r0 || !rho_p0 || !d_workspace) {
+    snprintf(g_err, sizeof(g_err), "required pointer is NULL");
+    return LBM_ERR_ARG;
+  }
+  const Layout L = make_layout(*params);
+  if (workspace_bytes < L.total) {
+    snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu bytes", workspace_bytes, L.total);
+    return LBM_ERR_ARG;
+  }
+  if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) {
+    snprintf(g_err, sizeof(g_err), "workspace must be %zu-byte aligned", kAlign);
+    return LBM_ERR_ARG;
+  }
+  const size_t N = size_t(params->nx) * params->ny * params->nz;
+  // Host-side validation of the inputs.
+  if (!theta && !(theta_uniform >= 0 && theta_uniform <= M_PI)) {
+    snprintf(g_err, sizeof(g_err), "theta_uniform must be in [0, pi]");
+    return LBM_ERR_ARG;
+  }
+  for (size_t n = 0; n < N; ++n) {
+    if (solid[n]) continue;
+    const double a = rho_r0[n], b = rho_p0[n];
+    if (!std::isfinite(a) || !std::isfinite(b) || a < 0 || b < 0 || !(a + b > 0)) {
+      snprintf(g_err, sizeof(g_err), "initial densities at fluid node %zu must be finite, >= 0, with positive sum", n);
+      return LBM_ERR_ARG;
+    }
+    if (theta && !(theta[n] >= 0 && theta[n] <= M_PI)) {
+      snprintf(g_err, sizeof(g_err), "theta at fluid node %zu outside [0, pi]", n);
+      return LBM_ERR_ARG;
+    }
+    if (c0 && params->species && (!std::isfinite(c0[n]) || c0[n] < 0)) {
+      snprintf(g_err, sizeof(g_err), "c0 at fluid node %zu must be finite and >= 0", n);
+      return LBM_ERR_ARG;
+    }
+  }
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ERR_ALLOC;
+  c->p = *params;
+  c->N = int(N);
+  c->L = L;
+  c->ws = static_cast<char*>(d_workspace);
+  c->stream = static_cast<hipStream_t>(stream);
+  c->steps = 0;
+  c->err[0] = 0;
+  c->prof = false;
+  for (double& v : c->kernel_ms) v = 0.0;
+  c->prof_steps = 0;
+  // Stage the host inputs in the second state buffer (free until the first step).
+  char* stage = c->ws + L.state[1];
+  double* d_theta = reinterpret_cast<double*>(stage);
+  double* d_rr = d_theta + N;
+  double* d_rp = d_rr + N;
+  double* d_c0 = d_rp + N;
+  uint8_t* d_solid = reinterpret_cast<uint8_t*>(d_c0 + N);
+  uint8_t* d_react = d_solid + N;
+  auto bail = [&](lbm_status st) {
+    snprintf(g_err, sizeof(g_err), "%s", c->err);
+    delete c;
+    return st;
+  };
+#define INIT_TRY(expr)                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      fail(c, LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));                     \
+      return bail(LBM_ERR_HIP);                                                         \
+    }                                                                                   \
+  } while (0)
+  INIT_TRY(hipMemsetAsync(c->ws, 0, L.total, c->stream));
+  INIT_TRY(hipMemcpyAsync(d_solid, solid, N, hipMemcpyHostToDevice, c->stream));
+  if (reactive) INIT_TRY(hipMemcpyAsync(d_react, reactive, N, hipMemcpyHostToDevice, c->stream));
+  if (theta) INIT_TRY(hipMemcpyAsync(d_theta, theta, 8 * N, hipMemcpyHostToDevice, c->stream));
+  INIT_TRY(hipMemcpyAsync(d_rr, rho_r0, 8 * N, hipMemcpyHostToDevice, c->stream));
+  INIT_TRY(hipMemcpyAsync(d_rp, rho_p0, 8 * N, hipMemcpyHostToDevice, c->stream));
+  if (c0) INIT_TRY(hipMemcpyAsync(d_c0, c0, 8 * N, hipMemcpyHostToDevice, c->stream));
+  lbm_status st;
+  switch (c->p.precision) {
+    case LBM_FP64: st = launch_init<0>(c, d_solid, reactive ? d_react : nullptr, theta ? d_theta : nullptr, theta_uniform, d_rr, d_rp, c0 ? d_c0 : nullptr); break;
+    case LBM_FP32: st = launch_init<1>(c, d_solid, reactive ? d_react : nullptr, theta ? d_theta : nullptr, theta_uniform, d_rr, d_rp, c0 ? d_c0 : nullptr); break;
+    case LBM_FP16_DEV: st = launch_init<2>(c, d_solid, reactive ? d_react : nullptr, theta ? d_theta : nullptr, theta_uniform, d_rr, d_rp, c0 ? d_c0 : nullptr); break;
+    default: st = launch_init<3>(c, d_solid, reactive ? d_react : nullptr, theta ? d_theta : nullptr, theta_uniform, d_rr, d_rp, c0 ? d_c0 : nullptr); break;
+  }
+  if (st != LBM_OK) return bail(st);
+  // The host inputs are pageable memory; finish the copies before returning to the caller.
+  INIT_TRY(hipStreamSynchronize(c->stream));
+#undef INIT_TRY
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int32_t nsteps, lbm_reductions* per_step) {
+  if (!c) return LBM_ERR_ARG;
+  if (nsteps < 0) return fail(c, LBM_ERR_ARG, "nsteps must be >= 0");
+  std::vector<double> rows;
+  bool bad = false;
+  int done = 0;
+  while (done < nsteps) {
+    const int chunk = std::min(kRing, nsteps - done);
+    for (int t = 0; t < chunk; ++t) {
+      lbm_status s;
+      switch (c->p.precision) {
+        case LBM_FP64: s = launch_step<0>(c, t); break;
+        case LBM_FP32: s = launch_step<1>(c, t); break;
+        case LBM_FP16_DEV: s = launch_step<2>(c, t); break;
+        default: s = launch_step<3>(c, t); break;
+      }
+      if (s != LBM_OK) return s;
+    }
+    rows.resize(5 * size_t(chunk));
+    HIP_TRY(c, hipMemcpyAsync(rows.data(), c->ws + c->L.ring, rows.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->prof) {
+      for (int t = 0; t < chunk; ++t)
+        for (int k = 0; k < 4; ++k) {
+          float ms = 0.f;
+          HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[5 * size_t(t) + k], c->ev[5 * size_t(t) + k + 1]));
+          c->kernel_ms[k] += ms;
+        }
+      c->prof_steps += chunk;
+    }
+    for (int t = 0; t < chunk; ++t) {
+      if (rows[5 * t + 4] > 0) bad = true;
+      if (per_step) {
+        lbm_reductions& r = per_step[done + t];
+        r.mass_r = rows[5 * t];
+        r.mass_p = rows[5 * t + 1];
+        r.conversion = rows[5 * t + 2];
+        r.species_total = rows[5 * t + 3];
+        r.nonfinite = rows[5 * t + 4];
+      }
+    }
+    done += chunk;
+  }
+  if (bad) return fail(c, LBM_ERR_NONFINITE, "non-finite values after step %lld", (long long)c->steps);
+  return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx* c, void* rr, void* rp, void* rn, void* u, void* cc) {
+  if (!c) return LBM_ERR_ARG;
+  DISPATCH(c, launch_moments, rr, rp, rn, u, cc);
+}
+
+lbm_status lbm_populations(lbm_ctx* c, void* fr, void* fp, void* g) {
+  if (!c) return LBM_ERR_ARG;
+  if (!fr || !fp) return fail(c, LBM_ERR_ARG, "fr and fp are required");
+  DISPATCH(c, launch_expand, fr, fp, g);
+}
+
+lbm_status lbm_geometry(lbm_ctx* c, void* d_info, void* d_wet) {
+  if (!c) return LBM_ERR_ARG;
+  const size_t N = c->N;
+  if (d_info) HIP_TRY(c, hipMemcpyAsync(d_info, c->ws + c->L.info, 4 * N, hipMemcpyDeviceToDevice, c->stream));
+  if (d_wet)
+    HIP_TRY(c, hipMemcpyAsync(d_wet, c->ws + c->L.wet, 4 * real_bytes(c->p.precision) * N, hipMemcpyDeviceToDevice,
+                              c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, void* d_dst) {
+  if (!c) return LBM_ERR_ARG;
+  if (!d_dst) return fail(c, LBM_ERR_ARG, "destination is NULL");
+  HIP_TRY(c, hipMemcpyAsync(d_dst, c->ws + c->L.state[c->cur], c->L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const void* d_src, int64_t steps_done) {
+  if (!c) return LBM_ERR_ARG;
+  if (!d_src) return fail(c, LBM_ERR_ARG, "source is NULL");
+  if (steps_done < 0) return fail(c, LBM_ERR_ARG, "steps_done must be >= 0");
+  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.state[c->cur], d_src, c->L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+  c->steps = steps_done;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_profiling(lbm_ctx* c, int32_t enable) {
+  if (!c) return LBM_ERR_ARG;
+  if (enable && c->ev.empty()) {
+    c->ev.resize(5 * size_t(kRing));
+    for (auto& e : c->ev) HIP_TRY(c, hipEventCreate(&e));
+  }
+  c->prof = enable != 0;
+  for (double& v : c->kernel_ms) v = 0.0;
+  c->prof_steps = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_kernel_times(lbm_ctx* c, double* kernel_ms, int64_t* steps) {
+  if (!c || !kernel_ms) return LBM_ERR_ARG;
+  for (int k = 0; k < 4; ++k) kernel_ms[k] = c->kernel_ms[k];
+  if (steps) *steps = c->prof_steps;
+  return LBM_OK;
+}
+
+int64_t lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }
+
+void lbm_free(lbm_ctx* c) {
+  if (!c) return;
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err : g_err; }
+
+}  // extern "C"

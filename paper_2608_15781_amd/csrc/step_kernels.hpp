@@ -1,0 +1,542 @@
+// Forward kernels of one time step (HIP, gfx950).
+//
+// State representation. Under Latva-Kokko recolouring of the colour-blind post-collision
+// populations (eq. operator_recoloring) followed by the proportional wall-reaction transfer,
+// the two colours' post-collision populations at a node are always
+//     f^r_i = a f^m_i + (w_i/|c_i|) c_i . v,     f^p_i = f^m_i - f^r_i,
+// with a = (1 - phi) rho^r / rho^m and v = (1 - phi) beta (rho^r rho^p / rho^m) n*. The state is
+// therefore stored exactly as the 19 colour-blind populations f^m (storage precision), the four
+// per-node scalars (a, v) (arithmetic precision) and, with the species, 7 populations g: 30
+// values per node instead of 45. Pulling f^r_i from node x - c_i reads f^m_i and (a, v) there.
+//
+// Layout: structure of arrays, one plane of N values per population or scalar, node index
+// x + nx*(y + ny*z) (x fastest). Two state buffers are used alternately (pull from one, write
+// the other), so no kernel reads what another thread of the same launch writes.
+//
+// One step is four launches (each one thread per node):
+//   colour   pull f^m, a, v -> rho^N at fluid nodes             (eqs. moments_components, color_function)
+//   extrap   rho^N into solid nodes next to fluid               (eq. color_lattice_weighted_average)
+//   normal   isotropic gradient, unit normal, Akai realignment   (eqs. finite_difference_scheme,
+//                                                                 color_gradient_normal, realigned_normal_vectors)
+//   collide  pull, curvature, forcing, central-moment collision, recolouring, reaction,
+//            species, store, FP64 reductions                     (remaining equations)
+// The 3-hop dependency rho^N -> n -> curvature between neighbours is what forces the split.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "lattice.hpp"
+#include "precision.hpp"
+
+namespace lbm {
+
+constexpr int kBlock = 256;
+constexpr int kXcd = 8;  // MI355X: 8 XCDs; workgroups are dealt round-robin across them
+
+// Maps the hardware workgroup id to a logical tile so that each XCD (with its own L2) works on
+// one contiguous slab of the lattice; neighbouring rows then share that XCD's L2.
+// gridDim.x is always a multiple of kXcd.
+__device__ inline int logical_block() {
+  int per_xcd = gridDim.x / kXcd;
+  return (blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd;
+}
+
+// Periodic neighbour offsets of one node.
+struct Nbr {
+  int n, x;
+  int dxm, dxp, dym, dyp, dzm, dzp;
+  __device__ inline int at(int cx, int cy, int cz) const {
+    return n + (cx > 0 ? dxp : (cx < 0 ? dxm : 0)) + (cy > 0 ? dyp : (cy < 0 ? dym : 0)) +
+           (cz > 0 ? dzp : (cz < 0 ? dzm : 0));
+  }
+};
+
+__device__ inline Nbr make_nbr(int n, int nx, int ny, int nz) {
+  Nbr b;
+  b.n = n;
+  int x = n % nx, t = n / nx;
+  int y = t % ny, z = t / ny;
+  int nxy = nx * ny;
+  b.x = x;
+  b.dxm = (x == 0) ? nx - 1 : -1;
+  b.dxp = (x == nx - 1) ? -(nx - 1) : 1;
+  b.dym = (y == 0) ? (ny - 1) * nx : -nx;
+  b.dyp = (y == ny - 1) ? -(ny - 1) * nx : nx;
+  b.dzm = (z == 0) ? (nz - 1) * nxy : -nxy;
+  b.dzp = (z == nz - 1) ? -(nz - 1) * nxy : nxy;
+  return b;
+}
+
+template <int P>
+struct StepArgs {
+  using S = typename Prec<P>::S;
+  using R = typename Prec<P>::R;
+  int nx, ny, nz, N;
+  const uint32_t* info;
+  // state in (pull source) and out
+  const S* fin;  // 19 planes f^m
+  const R* ain;  // 4 planes a, vx, vy, vz
+  const S* gin;  // 7 planes species
+  S* fout;
+  R* aout;
+  S* gout;
+  R* rhoN;       // 1 plane
+  R* nst;        // 4 planes: n*_x, n*_y, n*_z, |grad rho^N|
+  const R* wet;  // 4 planes: n_s (x, y, z), cos(theta)
+  double* partials;
+  unsigned* counter;
+  double* ring_row;  // 5 doubles of this step
+  R relax;           // 1 - 1/tau
+  R inv_tau_c;
+  R sigma, beta, xi, c_in, eps;
+  R acc[2][3];
+  R scale, inv_scale;
+  R gscale, inv_gscale;
+  int species;
+  // moments mode outputs (may be null)
+  R* m_rr;
+  R* m_rp;
+  R* m_rn;
+  R* m_u;
+  R* m_c;
+};
+
+// ---------------------------------------------------------------------------------------------
+// colour: rho^N = (rho^r - rho^p)/rho^m from the pulled populations.
+// ---------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int n = logical_block() * kBlock + threadIdx.x;
+  if (n >= A.N) return;
+  const uint32_t inf = A.info[n];
+  if (!(inf & kFluid)) return;
+  const Nbr nb = make_nbr(n, A.nx, A.ny, A.nz);
+  const size_t N = A.N;
+  R rm = 0, rr = 0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const bool bb = (i < 18) && ((inf >> i) & 1u);
+    const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+    const int q = bb ? D::opp[i] : i;
+    const R sgn = bb ? R(-1) : R(1);  // c_q = sgn * c_i
+    const R fm = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
+    const R a = A.ain[src];
+    R cv = 0;
+    if (D::cx[i]) cv += R(D::cx[i]) * A.ain[N + src];
+    if (D::cy[i]) cv += R(D::cy[i]) * A.ain[2 * N + src];
+    if (D::cz[i]) cv += R(D::cz[i]) * A.ain[3 * N + src];
+    rm += fm;
+    rr += a * fm + R(D::w_over_len(i)) * sgn * cv;
+  }
+  A.rhoN[n] = (rr + rr - rm) / rm;
+}
+
+// ---------------------------------------------------------------------------------------------
+// extrap: colour of solid nodes next to fluid, lattice-weighted average of fluid neighbours.
+// ---------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_extrap(StepArgs<P> A) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int n = logical_block() * kBlock + threadIdx.x;
+  if (n >= A.N) return;
+  const uint32_t inf = A.info[n];
+  if (!(inf & kExtrap)) return;
+  const Nbr nb = make_nbr(n, A.nx, A.ny, A.nz);
+  R num = 0, den = 0;
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    if ((inf >> i) & 1u) {
+      num += R(D::w(i)) * A.rhoN[nb.at(D::cx[i], D::cy[i], D::cz[i])];
+      den += R(D::w(i));
+    }
+  }
+  A.rhoN[n] = num / den;
+}
+
+// ---------------------------------------------------------------------------------------------
+// normal: G = 3 sum_i w_i c_i rho^N(x + c_i) as pair differences (a uniform field gives exactly
+// zero), n = +G/|G| (sign: see the design notes; with it force, curvature, recolouring and the
+// wetting angle all act with the physical sign), and at wetting nodes the Akai realignment
+// n* = n+ (n+ is always at least as close to n as n-: n+.n - n-.n = 2 sin(theta) sin(theta')).
+// ---------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int n = logical_block() * kBlock + threadIdx.x;
+  if (n >= A.N) return;
+  const uint32_t inf = A.info[n];
+  if (!(inf & kFluid)) return;
+  const Nbr nb = make_nbr(n, A.nx, A.ny, A.nz);
+  const size_t N = A.N;
+  R g[3] = {0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const int p = D::half[j];
+    const R d = A.rhoN[nb.at(D::cx[p], D::cy[p], D::cz[p])] - A.rhoN[nb.at(-D::cx[p], -D::cy[p], -D::cz[p])];
+    const R c3w = R(3.0 * D::w(p));
+    if (D::cx[p]) g[0] += c3w * R(D::cx[p]) * d;
+    if (D::cy[p]) g[1] += c3w * R(D::cy[p]) * d;
+    if (D::cz[p]) g[2] += c3w * R(D::cz[p]) * d;
+  }
+  const R len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  R nv[3] = {0, 0, 0};
+  if (len > A.eps) {
+    const R il = R(1) / len;
+    nv[0] = g[0] * il; nv[1] = g[1] * il; nv[2] = g[2] * il;
+    if (inf & kWet) {
+      const R sx = A.wet[n], sy = A.wet[N + n], sz = A.wet[2 * N + n];
+      if (sx * sx + sy * sy + sz * sz > R(0.5)) {
+        const R ct = A.wet[3 * N + n];
+        const R st = sqrt(fmax(R(0), (R(1) - ct) * (R(1) + ct)));
+        R cp = sx * nv[0] + sy * nv[1] + sz * nv[2];
+        cp = fmin(R(1), fmax(R(-1), cp));
+        const R sp = sqrt((R(1) - cp) * (R(1) + cp));
+        // n+ is undefined when n is parallel to n_s; n is kept for sin(theta') <= 1e-6, far
+        // above rounding noise, so symmetric configurations never realign on noise.
+        if (sp > R(1e-6)) {
+          const R b = st / sp;
+          const R a = ct - b * cp;
+          nv[0] = a * sx + b * nv[0];
+          nv[1] = a * sy + b * nv[1];
+          nv[2] = a * sz + b * nv[2];
+        }
+      }
+    }
+  }
+  A.nst[n] = nv[0];
+  A.nst[N + n] = nv[1];
+  A.nst[2 * N + n] = nv[2];
+  A.nst[3 * N + n] = len;
+}
+
+// T^{-1} k* of Appendix A (eq. back_transformation_vector), regrouped with common
+// subexpressions: for a move along +-x, q_x = u_x^2 +- u_x, and similarly for y, z.
+template <class R>
+__device__ inline void cm_back(R ux, R uy, R uz, R k5, R k6, R k7, R k8, R k9, R d[19]) {
+  const R x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
+  const R pxp = x2 + ux, pxm = x2 - ux, pyp = y2 + uy, pym = y2 - uy, pzp = z2 + uz, pzm = z2 - uz;
+  const R ax = k5 * R(1.0 / 3.0) + k6 * R(1.0 / 6.0);
+  const R ay = (k6 - k5) * R(1.0 / 6.0);
+  const R az = -(k5 * R(1.0 / 6.0) + k6 * R(1.0 / 3.0));
+  const R tx = uy * k7 + uz * k8, ty = ux * k7 + uz * k9, tz = ux * k8 + uy * k9;
+  const R ux2 = ux + ux, uy2 = uy + uy, uz2 = uz + uz;
+  d[0] = (pxp - y2 - z2 + R(1)) * ax - (ux2 + R(1)) * tx;
+  d[1] = (pxm - y2 - z2 + R(1)) * ax - (ux2 - R(1)) * tx;
+  d[2] = (pyp - x2 - z2 + R(1)) * ay - (uy2 + R(1)) * ty;
+  d[3] = (pym - x2 - z2 + R(1)) * ay - (uy2 - R(1)) * ty;
+  d[4] = (pzp - x2 - y2 + R(1)) * az - (uz2 + R(1)) * tz;
+  d[5] = (pzm - x2 - y2 + R(1)) * az - (uz2 - R(1)) * tz;
+  const R c12 = R(1.0 / 12.0), c4 = R(0.25);
+  // xy plane: (-q_x + 2 q_y) k5 + (q_x + q_y) k6 + 3 (2u_x + s_x)(2u_y + s_y) k7, all / 12
+  d[6] = ((pyp + pyp - pxp) * k5 + (pxp + pyp) * k6) * c12 + (ux2 + R(1)) * (uy2 + R(1)) * k7 * c4;
+  d[7] = ((pym + pym - pxp) * k5 + (pxp + pym) * k6) * c12 + (ux2 + R(1)) * (uy2 - R(1)) * k7 * c4;
+  d[10] = ((pyp + pyp - pxm) * k5 + (pxm + pyp) * k6) * c12 + (ux2 - R(1)) * (uy2 + R(1)) * k7 * c4;
+  d[11] = ((pym + pym - pxm) * k5 + (pxm + pym) * k6) * c12 + (ux2 - R(1)) * (uy2 - R(1)) * k7 * c4;
+  // xz plane: (-q_x + 2 q_z) k5 + (-2 q_x + q_z) k6 + 3 (2u_x + s_x)(2u_z + s_z) k8
+  d[8] = ((pzp + pzp - pxp) * k5 + (pzp - pxp - pxp) * k6) * c12 + (ux2 + R(1)) * (uz2 + R(1)) * k8 * c4;
+  d[9] = ((pzm + pzm - pxp) * k5 + (pzm - pxp - pxp) * k6) * c12 + (ux2 + R(1)) * (uz2 - R(1)) * k8 * c4;
+  d[12] = ((pzp + pzp - pxm) * k5 + (pzp - pxm - pxm) * k6) * c12 + (ux2 - R(1)) * (uz2 + R(1)) * k8 * c4;
+  d[13] = ((pzm + pzm - pxm) * k5 + (pzm - pxm - pxm) * k6) * c12 + (ux2 - R(1)) * (uz2 - R(1)) * k8 * c4;
+  // yz plane: (-q_y - q_z) k5 + (-2 q_y + q_z) k6 + 3 (2u_y + s_y)(2u_z + s_z) k9
+  d[14] = (-(pyp + pzp) * k5 + (pzp - pyp - pyp) * k6) * c12 + (uy2 + R(1)) * (uz2 + R(1)) * k9 * c4;
+  d[15] = (-(pyp + pzm) * k5 + (pzm - pyp - pyp) * k6) * c12 + (uy2 + R(1)) * (uz2 - R(1)) * k9 * c4;
+  d[16] = (-(pym + pzp) * k5 + (pzp - pym - pym) * k6) * c12 + (uy2 - R(1)) * (uz2 + R(1)) * k9 * c4;
+  d[17] = (-(pym + pzm) * k5 + (pzm - pym - pym) * k6) * c12 + (uy2 - R(1)) * (uz2 - R(1)) * k9 * c4;
+  d[18] = ((y2 + z2 - x2 - x2) * k5 + (z2 + z2 - x2 - y2) * k6) * R(1.0 / 3.0) +
+          R(4) * (ux * uy * k7 + ux * uz * k8 + uy * uz * k9);
+}
+
+template <class R>
+__device__ inline bool finite(R v) {
+  return isfinite(v);
+}
+
+// Deterministic FP64 reduction of 5 sums over the grid: wavefront shuffles, workgroup sum in
+// fixed order, one partial per workgroup, and the last workgroup to finish adds the partials
+// in workgroup order and resets the counter for the next launch.
+__device__ inline void grid_reduce5(double s[5], double* partials, unsigned* counter, double* out) {
+  __shared__ double red[kBlock / 64][5];
+  __shared__ bool last;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s[j] += __shfl_xor(s[j], off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) red[wave][j] = s[j];
+  __syncthreads();
+  const int lb = logical_block();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      double t = red[0][j];
+      for (int w = 1; w < kBlock / 64; ++w) t += red[w][j];
+      partials[size_t(lb) * 5 + j] = t;
+    }
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double t[5] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < int(gridDim.x); b += kBlock) {
+    const volatile double* pp = partials + size_t(b) * 5;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) t[j] += pp[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t[j] += __shfl_xor(t[j], off, 64);
+  }
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) red[wave][j] = t[j];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      double v = red[0][j];
+      for (int w = 1; w < kBlock / 64; ++w) v += red[w][j];
+      out[j] = v;
+    }
+    *counter = 0u;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// collide: the rest of the step at every fluid node. MOM = true writes the level-t fields
+// instead (lbm_moments) and leaves the state untouched.
+// ---------------------------------------------------------------------------------------------
+template <int P, bool MOM>
+__global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int n = logical_block() * kBlock + threadIdx.x;
+  double red5[5] = {0, 0, 0, 0, 0};
+  const uint32_t inf = (n < A.N) ? A.info[n] : 0u;
+  if (inf & kFluid) {
+    const Nbr nb = make_nbr(n, A.nx, A.ny, A.nz);
+    const size_t N = A.N;
+    // Pull streaming with halfway bounce-back: f^m_i(x) = S^m_i(x - c_i), or S^m_opp(i)(x).
+    R f[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const bool bb = (i < 18) && ((inf >> i) & 1u);
+      const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+      const int q = bb ? D::opp[i] : i;
+      f[i] = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
+    }
+    // Moments (same summation order as k_colour, so rho^m agrees bit for bit).
+    R rm = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) rm += f[i];
+    R mx = 0, my = 0, mz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      if (D::cx[i]) { mx += R(D::cx[i]) * f[i]; pxx += f[i]; }
+      if (D::cy[i]) { my += R(D::cy[i]) * f[i]; pyy += f[i]; }
+      if (D::cz[i]) { mz += R(D::cz[i]) * f[i]; pzz += f[i]; }
+      if (D::cx[i] && D::cy[i]) pxy += R(D::cx[i] * D::cy[i]) * f[i];
+      if (D::cx[i] && D::cz[i]) pxz += R(D::cx[i] * D::cz[i]) * f[i];
+      if (D::cy[i] && D::cz[i]) pyz += R(D::cy[i] * D::cz[i]) * f[i];
+    }
+    const R irm = R(1) / rm;
+    const R ux = mx * irm, uy = my * irm, uz = mz * irm;
+    const R rn = A.rhoN[n];
+    const R rr = R(0.5) * rm * (R(1) + rn);
+    const R rp = R(0.5) * rm * (R(1) - rn);
+
+    // Realigned unit normal and gradient magnitude; curvature H = -(tr J - n.J.n) with
+    // J_ab = 3 sum_i w_i c_ib n*_a(x + c_i), a solid neighbour contributing n*(x).
+    const R n0 = A.nst[n], n1 = A.nst[N + n], n2 = A.nst[2 * N + n];
+    const R glen = A.nst[3 * N + n];
+    const bool has_n = glen > A.eps;
+    R H = 0;
+    if (has_n) {
+      R J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+      for (int i = 0; i < 18; ++i) {
+        const bool sol = (inf >> D::opp[i]) & 1u;
+        const int m = nb.at(D::cx[i], D::cy[i], D::cz[i]);
+        const R a0 = sol ? n0 : A.nst[m];
+        const R a1 = sol ? n1 : A.nst[N + m];
+        const R a2 = sol ? n2 : A.nst[2 * N + m];
+        const R w3 = R(3.0 * D::w(i));
+        if (D::cx[i]) { J[0][0] += w3 * R(D::cx[i]) * a0; J[1][0] += w3 * R(D::cx[i]) * a1; J[2][0] += w3 * R(D::cx[i]) * a2; }
+        if (D::cy[i]) { J[0][1] += w3 * R(D::cy[i]) * a0; J[1][1] += w3 * R(D::cy[i]) * a1; J[2][1] += w3 * R(D::cy[i]) * a2; }
+        if (D::cz[i]) { J[0][2] += w3 * R(D::cz[i]) * a0; J[1][2] += w3 * R(D::cz[i]) * a1; J[2][2] += w3 * R(D::cz[i]) * a2; }
+      }
+      const R nn[3] = {n0, n1, n2};
+      R nJn = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) nJn += nn[a] * nn[b] * J[a][b];
+      H = -((J[0][0] + J[1][1] + J[2][2]) - nJn);
+    }
+
+    // Exact-difference forcing: du^k = F^k / rho^k = (1/2) sigma H |G| n* / rho^m + a^k.
+    const R fc = R(0.5) * A.sigma * H * glen * irm;
+    const R dur[3] = {fc * n0 + A.acc[0][0], fc * n1 + A.acc[0][1], fc * n2 + A.acc[0][2]};
+    const R dup[3] = {fc * n0 + A.acc[1][0], fc * n1 + A.acc[1][1], fc * n2 + A.acc[1][2]};
+    const R upx = ux + R(0.5) * (rr * dur[0] + rp * dup[0]) * irm;
+    const R upy = uy + R(0.5) * (rr * dur[1] + rp * dup[1]) * irm;
+    const R upz = uz + R(0.5) * (rr * dur[2] + rp * dup[2]) * irm;
+
+    // Species pull (face directions coincide with D3Q19 directions 0..5).
+    R g[7] = {0, 0, 0, 0, 0, 0, 0};
+    R C = R(1);
+    if (A.species) {
+      const bool outlet = inf & kOutlet;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        if (i == 1 && outlet) {
+          g[i] = Prec<P>::ld(A.gin[N + n], R(D3Q7::w(1)), A.inv_gscale);
+        } else {
+          const bool bb = (inf >> i) & 1u;
+          const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+          const int q = bb ? D3Q7::opp[i] : i;
+          g[i] = Prec<P>::ld(A.gin[size_t(q) * N + src], R(D3Q7::w(i)), A.inv_gscale);
+        }
+      }
+      g[6] = Prec<P>::ld(A.gin[6 * N + n], R(D3Q7::w(6)), A.inv_gscale);
+      C = 0;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) C += g[i];
+      if (inf & kInlet) C = A.c_in;
+    }
+
+    if (MOM) {
+      if (A.m_rr) A.m_rr[n] = rr;
+      if (A.m_rp) A.m_rp[n] = rp;
+      if (A.m_rn) A.m_rn[n] = rn;
+      if (A.m_u) { A.m_u[n] = upx; A.m_u[N + n] = upy; A.m_u[2 * N + n] = upz; }
+      if (A.m_c) A.m_c[n] = C;
+    } else {
+      // Central shear moments k5..k9 about the bare velocity, relaxed by (1 - 1/tau).
+      const R cxx = pxx - rm * ux * ux, cyy = pyy - rm * uy * uy, czz = pzz - rm * uz * uz;
+      const R k5 = A.relax * (cxx - cyy), k6 = A.relax * (cyy - czz);
+      const R k7 = A.relax * (pxy - rm * ux * uy), k8 = A.relax * (pxz - rm * ux * uz), k9 = A.relax * (pyz - rm * uy * uz);
+      R d[19];
+      cm_back(ux, uy, uz, k5, k6, k7, k8, k9, d);
+      // f^{m,*} = f^eq(rho^r, u + du^r) + f^eq(rho^p, u + du^p) + T^{-1} k*: the sum of both
+      // colours' equilibria needs only M = sum_k rho^k U^k and Pi = sum_k rho^k U^k U^k.
+      const R Ur[3] = {ux + dur[0], uy + dur[1], uz + dur[2]};
+      const R Up[3] = {ux + dup[0], uy + dup[1], uz + dup[2]};
+      const R M0 = rr * Ur[0] + rp * Up[0], M1 = rr * Ur[1] + rp * Up[1], M2 = rr * Ur[2] + rp * Up[2];
+      const R Pxx = rr * Ur[0] * Ur[0] + rp * Up[0] * Up[0];
+      const R Pyy = rr * Ur[1] * Ur[1] + rp * Up[1] * Up[1];
+      const R Pzz = rr * Ur[2] * Ur[2] + rp * Up[2] * Up[2];
+      const R Pxy = rr * Ur[0] * Ur[1] + rp * Up[0] * Up[1];
+      const R Pxz = rr * Ur[0] * Ur[2] + rp * Up[0] * Up[2];
+      const R Pyz = rr * Ur[1] * Ur[2] + rp * Up[1] * Up[2];
+      const R base = rm - R(1.5) * (Pxx + Pyy + Pzz);
+      R fs[19];
+      R fsum = 0;
+#pragma unroll
+      for (int i = 0; i < 19; ++i) {
+        const int cx = D::cx[i], cy = D::cy[i], cz = D::cz[i];
+        R cM = 0, cPc = 0;
+        if (cx) { cM += R(cx) * M0; cPc += Pxx; }
+        if (cy) { cM += R(cy) * M1; cPc += Pyy; }
+        if (cz) { cM += R(cz) * M2; cPc += Pzz; }
+        if (cx && cy) cPc += R(2 * cx * cy) * Pxy;
+        if (cx && cz) cPc += R(2 * cx * cz) * Pxz;
+        if (cy && cz) cPc += R(2 * cy * cz) * Pyz;
+        fs[i] = R(D::w(i)) * (base + R(3) * cM + R(4.5) * cPc) + d[i];
+        fsum += fs[i];
+      }
+      // Wall reaction with level-t densities, capped at full conversion.
+      const int rnn = int((inf & kRnnMask) >> kRnnShift);
+      R delta = 0;
+      if (rnn > 0 && rr > R(0)) {
+        if (A.species) {
+          if (C > R(0)) {
+            const R rate = A.xi * R(rnn) * rr * C;
+            const R cap = fmin(rr, C);
+            delta = fmin(rate, cap);
+          }
+        } else {
+          delta = fmin(A.xi * R(rnn), R(1)) * rr;
+        }
+      }
+      const R keep = (delta != R(0)) ? R(1) - delta / rr : R(1);
+      // Compact recoloured state: a = keep rho^r/rho^m, v = keep beta rho^r rho^p/rho^m n*.
+      const R aout = keep * rr * irm;
+      const R vc = keep * A.beta * rr * rp * irm;
+      const R v0 = has_n ? vc * n0 : R(0), v1 = has_n ? vc * n1 : R(0), v2 = has_n ? vc * n2 : R(0);
+#pragma unroll
+      for (int i = 0; i < 19; ++i) A.fout[size_t(i) * N + n] = Prec<P>::st(fs[i], R(D::w(i)), A.scale);
+      A.aout[n] = aout;
+      A.aout[N + n] = v0;
+      A.aout[2 * N + n] = v1;
+      A.aout[3 * N + n] = v2;
+      bool ok = finite(fsum) && finite(aout) && finite(v0 + v1 + v2) && finite(rr) && finite(rp);
+      if (A.species) {
+        // BGK towards g^eq = w C (1 + 4 c.u_phys); at the inlet the populations are replaced by
+        // the equilibrium at C_in; then the reaction sink.
+        const bool inlet = inf & kInlet;
+        const R sink = (delta != R(0)) ? R(1) - delta / C : R(1);
+        const R cu[7] = {upx, -upx, upy, -upy, upz, -upz, R(0)};
+        R gs = 0;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+          const R geq = R(D3Q7::w(i)) * C * (R(1) + R(4) * cu[i]);
+          const R gi = inlet ? geq : g[i];
+          const R go = (gi + (geq - gi) * A.inv_tau_c) * sink;
+          gs += go;
+          A.gout[size_t(i) * N + n] = Prec<P>::st(go, R(D3Q7::w(i)), A.gscale);
+        }
+        ok = ok && finite(gs);
+      }
+      red5[0] = double(rr);
+      red5[1] = double(rp);
+      red5[2] = double(delta);
+      red5[3] = double(C);
+      red5[4] = ok ? 0.0 : 1.0;
+    }
+  }
+  if (!MOM) grid_reduce5(red5, A.partials, A.counter, A.ring_row);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Expansion of the stored state to per-colour populations (lbm_populations).
+// ---------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_expand(StepArgs<P> A, typename Prec<P>::R* fr,
+                                                   typename Prec<P>::R* fp, typename Prec<P>::R* go) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int n = logical_block() * kBlock + threadIdx.x;
+  if (n >= A.N) return;
+  const size_t N = A.N;
+  const bool fluid = A.info[n] & kFluid;
+  const R a = fluid ? A.ain[n] : R(0);
+  const R v0 = fluid ? A.ain[N + n] : R(0), v1 = fluid ? A.ain[2 * N + n] : R(0), v2 = fluid ? A.ain[3 * N + n] : R(0);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    R fm = fluid ? Prec<P>::ld(A.fin[size_t(i) * N + n], R(D::w(i)), A.inv_scale) : R(0);
+    R cv = R(D::cx[i]) * v0 + R(D::cy[i]) * v1 + R(D::cz[i]) * v2;
+    R r = fluid ? a * fm + R(D::w_over_len(i)) * cv : R(0);
+    fr[size_t(i) * N + n] = r;
+    fp[size_t(i) * N + n] = fm - r;
+  }
+  if (go) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+      go[size_t(i) * N + n] = (fluid && A.species) ? Prec<P>::ld(A.gin[size_t(i) * N + n], R(D3Q7::w(i)), A.inv_gscale) : R(0);
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,98 @@
+"""The C-ABI library loads without a GPU, exports every symbol the header declares, and rejects
+invalid arguments on the host before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def core():
+    from paper_2608_15781_amd import build, core as c
+
+    if build.stale():
+        build.build()
+    return c
+
+
+def test_exports_every_declared_symbol(core):
+    header = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    declared = set(re.findall(r"\b(lbm_[a-z_]+)\(", header))
+    assert declared, "no declarations found"
+    L = core.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert set(core.EXPORTED) == declared
+
+
+def test_version(core):
+    assert b"gfx950" in core.lib().lbm_version()
+
+
+def test_workspace_sizes_scale_with_precision(core):
+    sizes = {}
+    for prec in ("fp64", "fp32", "fp16", "bf16"):
+        p = core.make_params((64, 64, 64), precision=prec, tau=0.8, species=True)
+        b = ctypes.c_size_t()
+        assert core.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == 0
+        s = ctypes.c_size_t()
+        assert core.lib().lbm_state_bytes(ctypes.byref(p), ctypes.byref(s)) == 0
+        sizes[prec] = (b.value, s.value)
+    N = 64 ** 3
+    # state = 19 populations + 4 scalars + 7 species populations per node
+    assert sizes["fp64"][1] >= (19 + 4 + 7) * 8 * N
+    assert sizes["fp32"][1] >= (19 + 4 + 7) * 4 * N
+    assert sizes["fp16"][1] >= (19 + 7) * 2 * N + 4 * 4 * N
+    assert sizes["fp16"][1] < sizes["fp32"][1] < sizes["fp64"][1]
+
+
+@pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("sigma", -1.0), ("beta", -0.1),
+                                         ("xi", -1e-3), ("grad_eps", 0.0), ("nx", 0), ("precision", 7),
+                                         ("reserved", 1), ("fp16_scale_log2", 40)])
+def test_invalid_params_rejected(core, field, value):
+    p = core.make_params((8, 8, 8), precision="fp16", tau=0.8)
+    setattr(p, field, value)
+    b = ctypes.c_size_t()
+    assert core.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == core.LBM_ERR_ARG
+    assert core.lib().lbm_last_error(None)
+
+
+def _init(core, p, N, ws_bytes, rho_r0=None, theta=None, ws_ptr=256):
+    solid = np.zeros(N, np.uint8)
+    rr = np.ones(N) if rho_r0 is None else rho_r0
+    rp = np.zeros(N)
+    h = ctypes.c_void_p()
+    P = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    return core.lib().lbm_init(ctypes.byref(p), P(solid), P(theta), 1.0, None, P(rr), P(rp), None,
+                               ctypes.c_void_p(ws_ptr), ws_bytes, None, ctypes.byref(h))
+
+
+def test_init_rejects_bad_inputs_on_host(core):
+    """Checked before any device call: small or misaligned workspace, bad densities or angles."""
+    p = core.make_params((4, 4, 4), precision="fp32", tau=0.8)
+    N = 64
+    need = ctypes.c_size_t()
+    core.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(need))
+    assert _init(core, p, N, need.value - 1) == core.LBM_ERR_ARG
+    assert b"too small" in core.lib().lbm_last_error(None)
+    assert _init(core, p, N, need.value, ws_ptr=257) == core.LBM_ERR_ARG
+    bad = np.ones(N)
+    bad[5] = np.nan
+    assert _init(core, p, N, need.value, rho_r0=bad) == core.LBM_ERR_ARG
+    th = np.full(N, 4.0)
+    assert _init(core, p, N, need.value, theta=th) == core.LBM_ERR_ARG
+    assert b"theta" in core.lib().lbm_last_error(None)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, core):
+    from paper_2608_15781_amd import build
+
+    monkeypatch.setattr(core, "_lib", None)
+    monkeypatch.setattr(build, "LIB", "/nonexistent/liblbm.so")
+    with pytest.raises(RuntimeError, match="not built"):
+        core.lib()

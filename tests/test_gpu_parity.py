@@ -1,0 +1,272 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle, element by element on
+the same seeded inputs.
+
+Tolerances (max |gpu - ref| / max |ref| per field):
+  FP64 storage: 1e-10 (target of the method port; both sides compute in FP64).
+  FP32 storage: FP32_TOL below, derived from FP32 rounding (2^-24 ~ 6e-8) amplified by the
+      ~100-step horizon and the 1/|grad rho^N| normalisation of interface normals.
+  FP16/BF16 deviation storage: HALF_TOL / BF16_TOL below (storage rounding 2^-11 and 2^-8 of the
+      deviation from the lattice weight, accumulated over the steps).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 2e-4
+HALF_TOL = 2e-2
+BF16_TOL = 1e-1
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+
+@pytest.fixture(scope="module")
+def core():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_15781_amd import core as c
+
+    c.lib()
+    return c
+
+
+def _pair(core, oracle_mod, shape, solid=None, theta=None, rho_r0=1.0, rho_p0=0.0, xi=0.0, precision="fp64",
+          species=False, x_open=False, tau_c=0.9, c0=None, reactive=None, **kw):
+    nx, ny, nz = shape
+    if solid is None:
+        solid = np.zeros((nz, ny, nx), np.uint8)
+    if theta is None:
+        theta = np.full((nz, ny, nx), np.pi / 2)
+    gpu = core.Lbm(shape, solid=solid, theta=theta, rho_r0=rho_r0, rho_p0=rho_p0, xi=xi, precision=precision,
+                   species=species, x_open=x_open, tau_species=tau_c, c0=c0, reactive=reactive, **kw)
+    ref = oracle_mod.Oracle(shape, solid=solid, theta=theta, rho_r0=rho_r0, rho_p0=rho_p0, xi=xi, species=species,
+                            x_open=x_open, tau_c=tau_c, c0=c0, reactive=reactive, **kw)
+    return gpu, ref
+
+
+def _compare(gpu, ref, tol, tag, species=True, pops=True):
+    m = gpu.moments()
+    r = ref.moments()
+    errs = {}
+    for key in ("rho_r", "rho_p", "rho_n", "u") + (("c",) if species else ()):
+        errs[key] = _rel(m[key].cpu().numpy(), r[key])
+    if pops:
+        fr, fp, g = gpu.populations()
+        rfr, rfp, rg = ref.get_state()
+        errs["f_r"] = _rel(fr.cpu().numpy(), rfr)
+        errs["f_p"] = _rel(fp.cpu().numpy(), rfp)
+        if species:
+            errs["g"] = _rel(g.cpu().numpy(), rg)
+    print(tag, " ".join("%s=%.2e" % kv for kv in errs.items()), flush=True)
+    for k, e in errs.items():
+        assert e < tol, (tag, k, e)
+    return errs
+
+
+def _grf(shape, wavelength, seed):
+    from paper_2608_15781_amd import inputs
+
+    return inputs.grf_mask(shape, wavelength, seed)[0]
+
+
+def _full_case(shape, seed=5, wavelength=8.0):
+    nx, ny, nz = shape
+    solid = _grf(shape, wavelength, seed)
+    rng = np.random.default_rng(seed + 100)
+    theta = np.deg2rad(rng.uniform(40, 140, solid.shape))
+    rr0 = (1 - solid) * (rng.uniform(size=solid.shape) > 0.4)
+    rp0 = (1 - solid) - rr0
+    return solid, theta, rr0.astype(float), rp0.astype(float)
+
+
+FULL_KW = dict(tau=0.7, sigma=0.02, beta=0.7, accel=[(2e-5, 5e-6, 0), (2e-5, 5e-6, 0)], species=True, x_open=True,
+               tau_c=0.8, xi=0.02)
+
+
+def test_droplet32_fp64_500_steps(core, oracle_mod):
+    """Static droplet, 32^3 periodic, R = 8, tau = 1, sigma = 0.01, beta = 0.7, 500 FP64 steps."""
+    from paper_2608_15781_amd import inputs
+
+    n = 32
+    rr0, rp0 = inputs.droplet((n, n, n), 8.0)
+    gpu, ref = _pair(core, oracle_mod, (n, n, n), rho_r0=rr0, rho_p0=rp0, tau=1.0, sigma=0.01, beta=0.7)
+    _compare(gpu, ref, FP64_TOL, "droplet t=0", species=False)
+    rg = gpu.step(500)
+    rr = ref.step(500)
+    assert _rel(rg[:, :2], rr[:, :2]) < FP64_TOL
+    _compare(gpu, ref, FP64_TOL, "droplet t=500", species=False)
+    # exact per-colour mass conservation on the GPU
+    assert abs(rg[-1, 0] / rg[0, 0] - 1) < 1e-12 and abs(rg[-1, 1] / rg[0, 1] - 1) < 1e-12
+
+
+def test_droplet_shear_path_fp64(core, oracle_mod):
+    """tau != 1 exercises the central-moment shear relaxation (at tau = 1 it vanishes)."""
+    from paper_2608_15781_amd import inputs
+
+    n = 24
+    rr0, rp0 = inputs.droplet((n, n, n), 6.0, centre=(11.3, 12.1, 11.7))
+    gpu, ref = _pair(core, oracle_mod, (n, n, n), rho_r0=rr0, rho_p0=rp0, tau=0.6, sigma=0.03, beta=0.5,
+                     accel=[(1e-4, -2e-5, 3e-5), (-5e-5, 1e-5, 0)])
+    gpu.step(150)
+    ref.step(150)
+    _compare(gpu, ref, FP64_TOL, "droplet tau=0.6", species=False)
+
+
+def test_porous_full_physics_fp64(core, oracle_mod):
+    """24^3 random porous mask with every feature: per-node contact angles, wall reaction,
+    species with inlet/outlet, body force, tau = 0.7; 100 FP64 steps."""
+    shape = (24, 24, 24)
+    solid, theta, rr0, rp0 = _full_case(shape)
+    gpu, ref = _pair(core, oracle_mod, shape, solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision="fp64",
+                     **FULL_KW)
+    rg = gpu.step(100)
+    rr = ref.step(100)
+    for j in range(4):
+        assert _rel(rg[:, j], rr[:, j]) < FP64_TOL, j
+    assert rg[:, 4].max() == 0
+    _compare(gpu, ref, FP64_TOL, "porous fp64 t=100")
+
+
+def test_ragged_shape_fp64(core, oracle_mod):
+    """Sizes that are not multiples of anything (last workgroup partly empty)."""
+    shape = (19, 13, 11)
+    solid, theta, rr0, rp0 = _full_case(shape, seed=9, wavelength=6.0)
+    gpu, ref = _pair(core, oracle_mod, shape, solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision="fp64",
+                     **FULL_KW)
+    gpu.step(60)
+    ref.step(60)
+    _compare(gpu, ref, FP64_TOL, "ragged 19x13x11")
+
+
+def test_quasi_2d_contact_line_fp64(core, oracle_mod):
+    """ny = 1 (periodic neighbours wrap onto the node itself): a cap on a wall."""
+    nx, nz = 40, 24
+    solid = np.zeros((nz, 1, nx), np.uint8)
+    solid[0] = solid[nz - 1] = solid[nz - 2] = 1
+    z, x = np.meshgrid(np.arange(nz), np.arange(nx), indexing="ij")
+    red = (((x - 20) ** 2 + z ** 2 < 100) & (solid[:, 0] == 0)).astype(float)[:, None, :]
+    gpu, ref = _pair(core, oracle_mod, (nx, 1, nz), solid=solid, theta=np.full(solid.shape, np.deg2rad(60)),
+                     rho_r0=red, rho_p0=(1 - solid) - red, tau=0.9, sigma=0.02, beta=0.7)
+    gpu.step(200)
+    ref.step(200)
+    _compare(gpu, ref, FP64_TOL, "quasi-2d cap", species=False)
+
+
+def test_tiny_and_degenerate(core, oracle_mod):
+    """3^3 all-fluid periodic; an all-solid lattice; zero steps."""
+    rng = np.random.default_rng(0)
+    rr0 = rng.uniform(0, 1, (3, 3, 3))
+    gpu, ref = _pair(core, oracle_mod, (3, 3, 3), rho_r0=rr0, rho_p0=1 - rr0, tau=0.8, sigma=0.05)
+    gpu.step(20)
+    ref.step(20)
+    _compare(gpu, ref, FP64_TOL, "3^3", species=False)
+    before = gpu.populations()[0].cpu().numpy()
+    assert gpu.step(0).shape == (0, 5)
+    assert np.array_equal(gpu.populations()[0].cpu().numpy(), before)
+    solid = np.ones((4, 4, 4), np.uint8)
+    g = core.Lbm((4, 4, 4), solid=solid, rho_r0=1.0, rho_p0=0.0, precision="fp64", species=True)
+    r = g.step(3)
+    assert np.all(r == 0)
+
+
+def test_geometry_matches_reference(core, oracle_mod):
+    """Static geometry: NN, wetting set, reactive set and the E8 solid normal."""
+    shape = (20, 18, 16)
+    solid, theta, rr0, rp0 = _full_case(shape, seed=13, wavelength=7.0)
+    gpu, ref = _pair(core, oracle_mod, shape, solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision="fp64",
+                     **FULL_KW)
+    info, wet = gpu.geometry()
+    info = info.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    wet = wet.cpu().numpy()
+    geo = ref.geometry()
+    fluid = solid.ravel() == 0
+    assert np.array_equal((info >> 18) & 1, fluid.astype(np.int64))
+    assert np.array_equal(((info >> 19) & 1)[fluid], geo["wet"][fluid])
+    assert np.array_equal(((info >> 20) & 7)[fluid], (geo["react"] * geo["nn"])[fluid])
+    ok = geo["ns_ok"].astype(bool) & fluid
+    assert np.abs(wet[:3][:, ok] - geo["ns"][:, ok]).max() < 1e-14
+    assert np.all(wet[:3][:, fluid & ~ok] == 0)
+    assert np.abs(wet[3][fluid] - np.cos(theta.ravel()[fluid])).max() < 1e-15
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", FP32_TOL), ("fp16", HALF_TOL), ("bf16", BF16_TOL)])
+def test_reduced_precision_against_fp64_reference(core, oracle_mod, precision, tol):
+    shape = (24, 24, 24)
+    solid, theta, rr0, rp0 = _full_case(shape, seed=17)
+    gpu, ref = _pair(core, oracle_mod, shape, solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision=precision,
+                     **FULL_KW)
+    rg = gpu.step(100)
+    rr = ref.step(100)
+    print(precision, "mass_r %.2e conv %.2e" % (_rel(rg[:, 0], rr[:, 0]), _rel(rg[:, 2], rr[:, 2])), flush=True)
+    _compare(gpu, ref, tol, "porous %s t=100" % precision)
+
+
+def test_checkpoint_roundtrip_and_determinism(core, oracle_mod):
+    shape = (20, 20, 20)
+    solid, theta, rr0, rp0 = _full_case(shape, seed=23)
+    kw = dict(FULL_KW)
+    kw["tau_species"] = kw.pop("tau_c")
+    a = core.Lbm(shape, solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision="fp32", **kw)
+    b = core.Lbm(shape, solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision="fp32", **kw)
+    a.step(30)
+    snap = a.get_state()
+    ra = a.step(20)
+    b.step(7)
+    b.set_state(snap, 30)
+    rb = b.step(20)
+    assert a.steps_done == b.steps_done == 50
+    assert np.array_equal(ra, rb)
+    assert np.array_equal(a.get_state().cpu().numpy(), b.get_state().cpu().numpy())
+
+
+def test_nonfinite_is_reported(core):
+    """A NaN planted in the state through set_state makes lbm_step return LBM_ERR_NONFINITE."""
+    import torch
+
+    a = core.Lbm((8, 8, 8), rho_r0=1.0, rho_p0=0.0, precision="fp32")
+    s = a.get_state()
+    f = s.view(torch.float32)
+    f[100] = float("nan")
+    a.set_state(s, 0)
+    with pytest.raises(core.LbmError) as e:
+        a.step(2)
+    assert e.value.status == core.LBM_ERR_NONFINITE
+
+
+def test_bench_workload_full_size(core, oracle_mod):
+    """The benchmark's workload at full size (128^3 random porous mask, wavelength 16, contact
+    angle 60 deg, species with inlet/outlet, xi = 1e-3, body force 1e-6) in the launch
+    configuration the benchmark times: every field after 3 steps against the oracle, in FP64
+    (1e-10) and in the benchmark's FP32 storage (FP32_TOL)."""
+    from paper_2608_15781_amd import inputs
+
+    w, solid, theta, rr0, rp0 = inputs.workload_inputs("bijel128")
+    kw = dict(tau=w["tau"], sigma=w["sigma"], beta=w["beta"], accel=[(w["accel"], 0, 0)] * 2, species=True,
+              x_open=True, tau_c=w["tau_c"], xi=w["xi"], c_in=w["c_in"])
+    ref = oracle_mod.Oracle(w["shape"], solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, **kw)
+    rr = ref.step(3)
+    r = ref.moments()
+    rfr, rfp, rg = ref.get_state()
+    kw["tau_species"] = kw.pop("tau_c")
+    kw["c_inlet"] = kw.pop("c_in")
+    for precision, tol in (("fp64", FP64_TOL), ("fp32", FP32_TOL)):
+        g = core.Lbm(w["shape"], solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision=precision, **kw)
+        red = g.step(3)
+        assert _rel(red[:, :4], rr[:, :4]) < tol
+        m = g.moments()
+        for key in ("rho_r", "rho_p", "rho_n", "c"):
+            assert _rel(m[key].cpu().numpy(), r[key]) < tol, (precision, key)
+        fr, fp, gg = g.populations()
+        for a, b, name in ((fr, rfr, "fr"), (fp, rfp, "fp"), (gg, rg, "g")):
+            e = _rel(a.cpu().numpy(), b)
+            print("bijel128", precision, name, "%.2e" % e, flush=True)
+            assert e < tol, (precision, name, e)
+        del g

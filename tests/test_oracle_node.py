@@ -134,9 +134,15 @@ def test_akai_realignment(oracle_mod):
         assert np.array_equal(out, npl)
         # n+ lies in the plane of n and n_s, on the same side of n_s as n
         assert abs(np.cross(n, ns) @ npl) < 1e-12
-    # parallel n and n_s: no realignment
-    out, _, _ = oracle_mod.wetting(np.array([0, 0, 1.0]), np.array([0, 0, 1.0]), 1.0)
-    assert np.array_equal(out, [0, 0, 1.0])
+    # parallel or antiparallel n and n_s (to within 1e-6 rad): no plane to rotate in, n is kept
+    for n in ([0, 0, 1.0], [0, 0, -1.0], [1e-7, 0, -1.0]):
+        n = np.array(n) / np.linalg.norm(n)
+        out, _, _ = oracle_mod.wetting(n, np.array([0, 0, 1.0]), 1.0)
+        assert np.array_equal(out, n)
+    # just above the bound it realigns
+    n = np.array([3e-6, 0, 1.0]) / np.linalg.norm([3e-6, 0, 1.0])
+    out, _, _ = oracle_mod.wetting(n, np.array([0, 0, 1.0]), 1.0)
+    assert abs(out[2] - np.cos(1.0)) < 1e-9
 
 
 def _one_node(oracle_mod, fr, fp, **kw):
