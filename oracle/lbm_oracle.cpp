@@ -212,10 +212,11 @@ void cm_back_transform(const T& ux, const T& uy, const T& uz, const T k[5], T d[
 
 // Akai wetting, eq. (realigned_normal_vectors): both candidates n+ and n-, then the one with the
 // smaller Euclidean distance to n (ties keep n+). theta' = arccos(n_s . n). The candidates divide
-// by sin(theta') and are undefined when n is parallel to n_s (no plane to rotate in); n is kept
-// whenever sin(theta') <= kAkaiSinMin, a bound far above rounding noise, so that the choice never
-// depends on the rounding of a near-zero perpendicular component.
-constexpr double kAkaiSinMin = 1e-6;
+// by sin(theta') and are undefined when n is parallel to n_s (no plane to rotate in). n is kept
+// whenever sin(theta') <= kAkaiSinMin = 1e-2 (n within 0.57 degrees of +-n_s: an interface
+// parallel to the wall, where the rotation plane is set by a sub-percent, noise-dominated
+// component of n). The bound caps the 1/sin(theta') amplification of rounding errors at 100.
+constexpr double kAkaiSinMin = 1e-2;
 
 template <class T>
 void wetting_realign(const T n[3], const double ns[3], const T& theta, T out[3], T np[3], T nm[3]) {

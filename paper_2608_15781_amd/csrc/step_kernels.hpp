@@ -196,9 +196,10 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
         R cp = sx * nv[0] + sy * nv[1] + sz * nv[2];
         cp = fmin(R(1), fmax(R(-1), cp));
         const R sp = sqrt((R(1) - cp) * (R(1) + cp));
-        // n+ is undefined when n is parallel to n_s; n is kept for sin(theta') <= 1e-6, far
-        // above rounding noise, so symmetric configurations never realign on noise.
-        if (sp > R(1e-6)) {
+        // n+ divides by sin(theta') and is undefined for n parallel to n_s; n is kept for
+        // sin(theta') <= 1e-2 (within 0.57 degrees of +-n_s), which caps the amplification of
+        // rounding errors in n at 100 and never realigns on a noise-dominated component.
+        if (sp > R(1e-2)) {
           const R b = st / sp;
           const R a = ct - b * cp;
           nv[0] = a * sx + b * nv[0];
