@@ -92,12 +92,20 @@ inline Dual acos(const Dual& a) {
 inline Dual cos(const Dual& a) { Dual r(std::cos(a.v)); double s = -std::sin(a.v); for (int k = 0; k < KD; ++k) r.d[k] = s * a.d[k]; return r; }
 inline Dual sin(const Dual& a) { Dual r(std::sin(a.v)); double c = std::cos(a.v); for (int k = 0; k < KD; ++k) r.d[k] = c * a.d[k]; return r; }
 
+inline Dual atan2(const Dual& y, const Dual& x) {
+  Dual r(std::atan2(y.v, x.v));
+  double den = x.v * x.v + y.v * y.v;
+  for (int k = 0; k < KD; ++k) r.d[k] = (den > 0.0) ? (x.v * y.d[k] - y.v * x.d[k]) / den : 0.0;
+  return r;
+}
+
 inline double val(double x) { return x; }
 inline double val(const Dual& x) { return x.v; }
 using std::sqrt;
 using std::acos;
 using std::cos;
 using std::sin;
+using std::atan2;
 
 // ---------------------------------------------------------------------------------------------
 // Lattice (Sec. II.A): D3Q19 velocities are the columns of the matrix M, the rest vector last;
@@ -211,24 +219,25 @@ void cm_back_transform(const T& ux, const T& uy, const T& uz, const T k[5], T d[
 }
 
 // Akai wetting, eq. (realigned_normal_vectors): both candidates n+ and n-, then the one with the
-// smaller Euclidean distance to n (ties keep n+). theta' = arccos(n_s . n). The candidates divide
-// by sin(theta') and are undefined when n is parallel to n_s (no plane to rotate in). n is kept
-// whenever sin(theta') <= kAkaiSinMin = 1e-2 (n within 0.57 degrees of +-n_s: an interface
-// parallel to the wall, where the rotation plane is set by a sub-percent, noise-dominated
-// component of n). The bound caps the 1/sin(theta') amplification of rounding errors at 100.
-constexpr double kAkaiSinMin = 1e-2;
+// smaller Euclidean distance to n (ties keep n+). theta' = arccos(n_s . n). Writing
+// t = (n - cos(theta') n_s) / sin(theta') (unit vector in the plane of n and n_s, perpendicular to
+// n_s), the candidates are n+- = cos(+-theta) n_s + sin(+-theta) t: n rotated in that plane to the
+// angle +-theta. They are undefined for n parallel to n_s, and the rotation plane is set by the
+// component of n perpendicular to n_s. n is kept whenever sin(theta') < kAkaiCone = 1e-2 (n within
+// 0.57 degrees of +-n_s, an interface parallel to the wall): there the perpendicular component is
+// too small to define a plane, and rotating on it would feed rounding noise into the colour field
+// (the realigned normal drives recolouring along itself, so any gain above one near the axis grows
+// the noise from step to step). The bound also caps the 1/sin(theta') amplification at 100.
+constexpr double kAkaiCone = 1e-2;
 
 template <class T>
 void wetting_realign(const T n[3], const double ns[3], const T& theta, T out[3], T np[3], T nm[3]) {
-  T dot = n[0] * ns[0] + n[1] * ns[1] + n[2] * ns[2];
-  if (val(dot) > 1.0) dot = T(1.0);
-  if (val(dot) < -1.0) dot = T(-1.0);
-  T thp = acos(dot);
-  T sthp = sin(thp);
+  T cthp = n[0] * ns[0] + n[1] * ns[1] + n[2] * ns[2];
+  T cr[3] = {n[1] * ns[2] - n[2] * ns[1], n[2] * ns[0] - n[0] * ns[2], n[0] * ns[1] - n[1] * ns[0]};
+  T sthp = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
   for (int a = 0; a < 3; ++a) { out[a] = n[a]; np[a] = n[a]; nm[a] = n[a]; }
-  if (!(val(sthp) > kAkaiSinMin)) return;
-  T cthp = cos(thp);
-  T cp = cos(theta), sp = sin(theta);          // cos(+theta), sin(+theta)
+  if (!(val(sthp) > 0.0)) return;  // exactly parallel: no plane, n is its own limit
+  T cp = cos(theta), sp = sin(theta);                // cos(+theta), sin(+theta)
   T cm = cos(-1.0 * theta), sm = sin(-1.0 * theta);  // cos(-theta), sin(-theta)
   for (int a = 0; a < 3; ++a) {
     np[a] = (cp - sp * cthp / sthp) * ns[a] + (sp / sthp) * n[a];
@@ -239,7 +248,9 @@ void wetting_realign(const T n[3], const double ns[3], const T& theta, T out[3],
     double ep = val(np[a]) - val(n[a]), em = val(nm[a]) - val(n[a]);
     dp += ep * ep; dm += em * em;
   }
-  for (int a = 0; a < 3; ++a) out[a] = (dm < dp) ? nm[a] : np[a];
+  const bool minus = dm < dp;
+  if (val(sthp) < kAkaiCone) return;  // inside the cone around +-n_s: n is kept
+  for (int a = 0; a < 3; ++a) out[a] = minus ? nm[a] : np[a];
 }
 
 struct Params {

@@ -28,9 +28,9 @@ size_t store_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precisio
 size_t real_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 
 struct Layout {
-  size_t info, wet, rhoN, nst, state[2], partials, counter, ring, total;
+  size_t info, wet, rhoN, nst, state[2], partials, ring, lists[2], counts, total;
   size_t f_off, a_off, g_off, state_bytes;  // within one state buffer
-  int nblocks;
+  int nblocks;  // one thread per node, rounded up to a multiple of kXcd workgroups
 };
 
 Layout make_layout(const lbm_params& p) {
@@ -52,8 +52,10 @@ Layout make_layout(const lbm_params& p) {
   L.state[0] = o; o = align_up(o + L.state_bytes);
   L.state[1] = o; o = align_up(o + L.state_bytes);
   L.partials = o; o = align_up(o + 5 * sizeof(double) * size_t(nb));
-  L.counter = o; o = align_up(o + sizeof(unsigned));
   L.ring = o; o = align_up(o + 5 * sizeof(double) * kRing);
+  L.lists[0] = o; o = align_up(o + 4 * N);  // fluid nodes
+  L.lists[1] = o; o = align_up(o + 4 * N);  // solid nodes with extrapolated colour
+  L.counts = o; o = align_up(o + 4 * (size_t(nb) + 2));
   L.total = o;
   return L;
 }
@@ -68,6 +70,8 @@ struct lbm_ctx {
   hipStream_t stream;
   int cur;  // index of the state buffer holding S_t
   int64_t steps;
+  int nfluid, next;      // list lengths
+  int nb_fluid, nb_ext;  // workgroups over each list (multiples of kXcd, 0 if empty)
   char err[512];
   // Profiling: 5 events per step of the current chunk (before colour, after each kernel).
   bool prof;
@@ -217,6 +221,63 @@ __global__ void k_init_state(StepArgs<P> A, const double* rr0, const double* rp0
   }
 }
 
+// Order-preserving stream compaction of the nodes whose info word has any bit of `mask`:
+// per-workgroup counts, one-workgroup exclusive scan, scatter with wavefront ballots.
+__global__ void k_flag_count(const uint32_t* info, int N, uint32_t mask, int* counts) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = __syncthreads_count(n < N && (info[n] & mask));
+  if (threadIdx.x == 0) counts[blockIdx.x] = c;
+}
+
+__global__ void k_scan_counts(int* counts, int nb) {
+  __shared__ int part[1024];
+  const int chunk = (nb + 1023) / 1024;
+  const int b0 = threadIdx.x * chunk, b1 = min(nb, b0 + chunk);
+  int sum = 0;
+  for (int b = b0; b < b1; ++b) sum += counts[b];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < 1024; ++i) { const int v = part[i]; part[i] = run; run += v; }
+    counts[nb] = run;
+  }
+  __syncthreads();
+  int run = part[threadIdx.x];
+  for (int b = b0; b < b1; ++b) { const int v = counts[b]; counts[b] = run; run += v; }
+}
+
+__global__ void k_flag_scatter(const uint32_t* info, int N, uint32_t mask, const int* offsets, int* list) {
+  __shared__ int wsum[4];
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool f = n < N && (info[n] & mask);
+  const unsigned long long bal = __ballot(f);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int pre = __popcll(bal & below);
+  if (lane == 0) wsum[wave] = __popcll(bal);
+  __syncthreads();
+  int off = offsets[blockIdx.x];
+  for (int w = 0; w < wave; ++w) off += wsum[w];
+  if (f) list[off + pre] = n;
+}
+
+FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t s = 0;
+  while ((uint64_t(1) << s) < d) ++s;
+  f.s = s;
+  f.m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << s) - d)) / d + 1);
+  return f;
+}
+
+int rounded_blocks(int n) {
+  if (n <= 0) return 0;
+  const int nb = (n + kBlock - 1) / kBlock;
+  return (nb + kXcd - 1) / kXcd * kXcd;
+}
+
 // ------------------------------------------------------------------------------------------
 // Launch helpers
 // ------------------------------------------------------------------------------------------
@@ -229,6 +290,13 @@ StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
   const lbm_params& p = c->p;
   const Layout& L = c->L;
   A.nx = p.nx; A.ny = p.ny; A.nz = p.nz; A.N = c->N;
+  A.geo.nx = p.nx; A.geo.ny = p.ny; A.geo.nz = p.nz;
+  A.geo.fx = make_fastdiv(uint32_t(p.nx));
+  A.geo.fy = make_fastdiv(uint32_t(p.ny));
+  A.fluid = reinterpret_cast<const int*>(c->ws + L.lists[0]);
+  A.nfluid = c->nfluid;
+  A.ext = reinterpret_cast<const int*>(c->ws + L.lists[1]);
+  A.next = c->next;
   A.info = reinterpret_cast<const uint32_t*>(c->ws + L.info);
   char* sb = c->ws + L.state[src_buf];
   char* db = c->ws + L.state[1 - src_buf];
@@ -242,7 +310,6 @@ StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
   A.nst = reinterpret_cast<R*>(c->ws + L.nst);
   A.wet = reinterpret_cast<const R*>(c->ws + L.wet);
   A.partials = reinterpret_cast<double*>(c->ws + L.partials);
-  A.counter = reinterpret_cast<unsigned*>(c->ws + L.counter);
   A.ring_row = reinterpret_cast<double*>(c->ws + L.ring);
   A.relax = R(1.0 - 1.0 / p.tau);
   A.inv_tau_c = p.species ? R(1.0 / p.tau_species) : R(1);
@@ -263,16 +330,18 @@ lbm_status launch_step(lbm_ctx* c, int slot) {
   StepArgs<P> A = make_args<P>(c, c->cur);
   A.ring_row = reinterpret_cast<double*>(c->ws + c->L.ring) + 5 * size_t(slot);
   const dim3 grid(c->L.nblocks), block(kBlock);
+  const dim3 gf(c->nb_fluid), ge(c->nb_ext);
   hipEvent_t* ev = c->prof ? &c->ev[5 * size_t(slot)] : nullptr;
   if (ev) HIP_TRY(c, hipEventRecord(ev[0], c->stream));
-  hipLaunchKernelGGL(k_colour<P>, grid, block, 0, c->stream, A);
+  if (c->nb_fluid) hipLaunchKernelGGL(k_colour<P>, gf, block, 0, c->stream, A);
   if (ev) HIP_TRY(c, hipEventRecord(ev[1], c->stream));
-  hipLaunchKernelGGL(k_extrap<P>, grid, block, 0, c->stream, A);
+  if (c->nb_ext) hipLaunchKernelGGL(k_extrap<P>, ge, block, 0, c->stream, A);
   if (ev) HIP_TRY(c, hipEventRecord(ev[2], c->stream));
-  hipLaunchKernelGGL(k_normal<P>, grid, block, 0, c->stream, A);
+  if (c->nb_fluid) hipLaunchKernelGGL(k_normal<P>, gf, block, 0, c->stream, A);
   if (ev) HIP_TRY(c, hipEventRecord(ev[3], c->stream));
-  hipLaunchKernelGGL((k_collide<P, false>), grid, block, 0, c->stream, A);
+  if (c->nb_fluid) hipLaunchKernelGGL((k_collide<P, false>), gf, block, 0, c->stream, A);
   if (ev) HIP_TRY(c, hipEventRecord(ev[4], c->stream));
+  hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kFinish), 0, c->stream, A.partials, c->nb_fluid, A.ring_row);
   HIP_TRY(c, hipGetLastError());
   c->cur = 1 - c->cur;
   c->steps++;
@@ -290,11 +359,11 @@ lbm_status launch_moments(lbm_ctx* c, void* rr, void* rp, void* rn, void* u, voi
   for (void* ptr : {rr, rp, rn, cc})
     if (ptr) HIP_TRY(c, hipMemsetAsync(ptr, 0, rb * N, c->stream));
   if (u) HIP_TRY(c, hipMemsetAsync(u, 0, 3 * rb * N, c->stream));
-  const dim3 grid(c->L.nblocks), block(kBlock);
-  hipLaunchKernelGGL(k_colour<P>, grid, block, 0, c->stream, A);
-  hipLaunchKernelGGL(k_extrap<P>, grid, block, 0, c->stream, A);
-  hipLaunchKernelGGL(k_normal<P>, grid, block, 0, c->stream, A);
-  hipLaunchKernelGGL((k_collide<P, true>), grid, block, 0, c->stream, A);
+  const dim3 gf(c->nb_fluid), ge(c->nb_ext), block(kBlock);
+  if (c->nb_fluid) hipLaunchKernelGGL(k_colour<P>, gf, block, 0, c->stream, A);
+  if (c->nb_ext) hipLaunchKernelGGL(k_extrap<P>, ge, block, 0, c->stream, A);
+  if (c->nb_fluid) hipLaunchKernelGGL(k_normal<P>, gf, block, 0, c->stream, A);
+  if (c->nb_fluid) hipLaunchKernelGGL((k_collide<P, true>), gf, block, 0, c->stream, A);
   HIP_TRY(c, hipGetLastError());
   return LBM_OK;
 }
@@ -321,6 +390,22 @@ lbm_status launch_init(lbm_ctx* c, const uint8_t* d_solid, const uint8_t* d_reac
                      int(p.species && p.x_open), info);
   hipLaunchKernelGGL(k_init_wet<R>, dim3(gb), dim3(tb), 0, c->stream, p.nx, p.ny, p.nz, d_solid, info, d_theta,
                      theta_uniform, reinterpret_cast<R*>(c->ws + c->L.wet));
+  // Launch lists: fluid nodes and solid nodes with extrapolated colour, in node order.
+  int* counts = reinterpret_cast<int*>(c->ws + c->L.counts);
+  const uint32_t masks[2] = {kFluid, kExtrap};
+  int lens[2] = {0, 0};
+  for (int k = 0; k < 2; ++k) {
+    int* list = reinterpret_cast<int*>(c->ws + c->L.lists[k]);
+    hipLaunchKernelGGL(k_flag_count, dim3(gb), dim3(tb), 0, c->stream, info, c->N, masks[k], counts);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, c->stream, counts, gb);
+    hipLaunchKernelGGL(k_flag_scatter, dim3(gb), dim3(tb), 0, c->stream, info, c->N, masks[k], counts, list);
+    HIP_TRY(c, hipMemcpyAsync(&lens[k], counts + gb, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  c->nfluid = lens[0];
+  c->next = lens[1];
+  c->nb_fluid = rounded_blocks(c->nfluid);
+  c->nb_ext = rounded_blocks(c->next);
   // The initial state goes into buffer 0 (make_args with src 1 writes buffer 0).
   StepArgs<P> A = make_args<P>(c, 1);
   hipLaunchKernelGGL(k_init_state<P>, dim3(gb), dim3(tb), 0, c->stream, A, d_rr, d_rp, d_c0);

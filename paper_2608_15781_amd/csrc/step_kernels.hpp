@@ -52,12 +52,26 @@ struct Nbr {
   }
 };
 
-__device__ inline Nbr make_nbr(int n, int nx, int ny, int nz) {
+// Division by a runtime constant d for 0 <= n < 2^31: q = (umulhi(n, m) + n) >> s with
+// s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1 (computed on the host).
+struct FastDiv {
+  uint32_t d, m, s;
+  __device__ inline uint32_t div(uint32_t n) const { return (__umulhi(n, m) + n) >> s; }
+};
+
+struct Geom {
+  int nx, ny, nz;
+  FastDiv fx, fy;
+};
+
+__device__ inline Nbr make_nbr(int n, const Geom& g) {
   Nbr b;
   b.n = n;
-  int x = n % nx, t = n / nx;
-  int y = t % ny, z = t / ny;
-  int nxy = nx * ny;
+  const uint32_t t = g.fx.div(uint32_t(n));
+  const int x = n - int(t) * g.nx;
+  const int z = int(g.fy.div(t));
+  const int y = int(t) - z * g.ny;
+  const int nx = g.nx, ny = g.ny, nz = g.nz, nxy = nx * ny;
   b.x = x;
   b.dxm = (x == 0) ? nx - 1 : -1;
   b.dxp = (x == nx - 1) ? -(nx - 1) : 1;
@@ -73,6 +87,11 @@ struct StepArgs {
   using S = typename Prec<P>::S;
   using R = typename Prec<P>::R;
   int nx, ny, nz, N;
+  Geom geo;
+  const int* fluid;  // dense indices of the fluid nodes, in increasing order
+  int nfluid;
+  const int* ext;    // dense indices of the solid nodes whose colour is extrapolated
+  int next;
   const uint32_t* info;
   // state in (pull source) and out
   const S* fin;  // 19 planes f^m
@@ -85,7 +104,6 @@ struct StepArgs {
   R* nst;        // 4 planes: n*_x, n*_y, n*_z, |grad rho^N|
   const R* wet;  // 4 planes: n_s (x, y, z), cos(theta)
   double* partials;
-  unsigned* counter;
   double* ring_row;  // 5 doubles of this step
   R relax;           // 1 - 1/tau
   R inv_tau_c;
@@ -109,11 +127,11 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int n = logical_block() * kBlock + threadIdx.x;
-  if (n >= A.N) return;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  if (t >= A.nfluid) return;
+  const int n = A.fluid[t];
   const uint32_t inf = A.info[n];
-  if (!(inf & kFluid)) return;
-  const Nbr nb = make_nbr(n, A.nx, A.ny, A.nz);
+  const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
   R rm = 0, rr = 0;
 #pragma unroll
@@ -141,11 +159,11 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs<P> A) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int n = logical_block() * kBlock + threadIdx.x;
-  if (n >= A.N) return;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  if (t >= A.next) return;
+  const int n = A.ext[t];
   const uint32_t inf = A.info[n];
-  if (!(inf & kExtrap)) return;
-  const Nbr nb = make_nbr(n, A.nx, A.ny, A.nz);
+  const Nbr nb = make_nbr(n, A.geo);
   R num = 0, den = 0;
 #pragma unroll
   for (int i = 0; i < 18; ++i) {
@@ -167,11 +185,11 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int n = logical_block() * kBlock + threadIdx.x;
-  if (n >= A.N) return;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  if (t >= A.nfluid) return;
+  const int n = A.fluid[t];
   const uint32_t inf = A.info[n];
-  if (!(inf & kFluid)) return;
-  const Nbr nb = make_nbr(n, A.nx, A.ny, A.nz);
+  const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
   R g[3] = {0, 0, 0};
 #pragma unroll
@@ -193,13 +211,15 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
       if (sx * sx + sy * sy + sz * sz > R(0.5)) {
         const R ct = A.wet[3 * N + n];
         const R st = sqrt(fmax(R(0), (R(1) - ct) * (R(1) + ct)));
-        R cp = sx * nv[0] + sy * nv[1] + sz * nv[2];
-        cp = fmin(R(1), fmax(R(-1), cp));
-        const R sp = sqrt((R(1) - cp) * (R(1) + cp));
-        // n+ divides by sin(theta') and is undefined for n parallel to n_s; n is kept for
-        // sin(theta') <= 1e-2 (within 0.57 degrees of +-n_s), which caps the amplification of
-        // rounding errors in n at 100 and never realigns on a noise-dominated component.
-        if (sp > R(1e-2)) {
+        // cos and sin of theta' from the dot and cross products (accurate next to +-n_s).
+        const R cp = sx * nv[0] + sy * nv[1] + sz * nv[2];
+        const R q0 = nv[1] * sz - nv[2] * sy, q1 = nv[2] * sx - nv[0] * sz, q2 = nv[0] * sy - nv[1] * sx;
+        const R sp = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
+        // n+ = cos(theta) n_s + sin(theta) t, t = (n - cos(theta') n_s)/sin(theta'): n rotated in
+        // the plane of n and n_s to the angle theta. Within sin(theta') < 1e-2 of +-n_s that plane
+        // is not defined by n (an interface parallel to the wall) and n is kept; this also caps
+        // the 1/sin(theta') amplification of rounding at 100.
+        if (sp >= R(1e-2)) {
           const R b = st / sp;
           const R a = ct - b * cp;
           nv[0] = a * sx + b * nv[0];
@@ -257,12 +277,11 @@ __device__ inline bool finite(R v) {
   return isfinite(v);
 }
 
-// Deterministic FP64 reduction of 5 sums over the grid: wavefront shuffles, workgroup sum in
-// fixed order, one partial per workgroup, and the last workgroup to finish adds the partials
-// in workgroup order and resets the counter for the next launch.
-__device__ inline void grid_reduce5(double s[5], double* partials, unsigned* counter, double* out) {
+// Deterministic FP64 reduction of 5 sums: wavefront shuffles, then the workgroup's waves in
+// fixed order; one partial per workgroup (plain stores, no fences or atomics). k_finish_reduce,
+// launched after the grid on the same stream, adds the partials in workgroup order.
+__device__ inline void block_reduce5(double s[5], double* partials) {
   __shared__ double red[kBlock / 64][5];
-  __shared__ bool last;
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
 #pragma unroll
@@ -273,33 +292,41 @@ __device__ inline void grid_reduce5(double s[5], double* partials, unsigned* cou
 #pragma unroll
     for (int j = 0; j < 5; ++j) red[wave][j] = s[j];
   __syncthreads();
-  const int lb = logical_block();
   if (threadIdx.x == 0) {
+    const int lb = logical_block();
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
       double t = red[0][j];
-      for (int w = 1; w < kBlock / 64; ++w) t += red[w][j];
-      partials[size_t(lb) * 5 + j] = t;
-    }
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double t[5] = {0, 0, 0, 0, 0};
-  for (int b = threadIdx.x; b < int(gridDim.x); b += kBlock) {
-    const volatile double* pp = partials + size_t(b) * 5;
 #pragma unroll
-    for (int j = 0; j < 5; ++j) t[j] += pp[j];
+      for (int w = 1; w < kBlock / 64; ++w) t += red[w][j];
+      partials[size_t(j) * gridDim.x + lb] = t;
+    }
+  }
+}
+
+constexpr int kFinish = 1024;
+
+__global__ __launch_bounds__(kFinish) void k_finish_reduce(const double* partials, int nparts, double* out) {
+  __shared__ double red[kFinish / 64][5];
+  double t[5] = {0, 0, 0, 0, 0};
+  int b = threadIdx.x;
+  for (; b + 3 * kFinish < nparts; b += 4 * kFinish) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const double* p = partials + size_t(j) * nparts;
+      t[j] += ((p[b] + p[b + kFinish]) + (p[b + 2 * kFinish] + p[b + 3 * kFinish]));
+    }
+  }
+  for (; b < nparts; b += kFinish) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) t[j] += partials[size_t(j) * nparts + b];
   }
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) t[j] += __shfl_xor(t[j], off, 64);
   }
-  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0)
 #pragma unroll
     for (int j = 0; j < 5; ++j) red[wave][j] = t[j];
@@ -308,10 +335,9 @@ __device__ inline void grid_reduce5(double s[5], double* partials, unsigned* cou
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
       double v = red[0][j];
-      for (int w = 1; w < kBlock / 64; ++w) v += red[w][j];
+      for (int w = 1; w < kFinish / 64; ++w) v += red[w][j];
       out[j] = v;
     }
-    *counter = 0u;
   }
 }
 
@@ -323,11 +349,12 @@ template <int P, bool MOM>
 __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int n = logical_block() * kBlock + threadIdx.x;
+  const int t = logical_block() * kBlock + threadIdx.x;
   double red5[5] = {0, 0, 0, 0, 0};
-  const uint32_t inf = (n < A.N) ? A.info[n] : 0u;
+  const int n = (t < A.nfluid) ? A.fluid[t] : 0;
+  const uint32_t inf = (t < A.nfluid) ? A.info[n] : 0u;
   if (inf & kFluid) {
-    const Nbr nb = make_nbr(n, A.nx, A.ny, A.nz);
+    const Nbr nb = make_nbr(n, A.geo);
     const size_t N = A.N;
     // Pull streaming with halfway bounce-back: f^m_i(x) = S^m_i(x - c_i), or S^m_opp(i)(x).
     R f[19];
@@ -508,7 +535,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
       red5[4] = ok ? 0.0 : 1.0;
     }
   }
-  if (!MOM) grid_reduce5(red5, A.partials, A.counter, A.ring_row);
+  if (!MOM) block_reduce5(red5, A.partials);
 }
 
 // ---------------------------------------------------------------------------------------------

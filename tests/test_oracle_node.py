@@ -128,24 +128,30 @@ def test_akai_realignment(oracle_mod):
         ns /= np.linalg.norm(ns)
         th = rng.uniform(0.01, np.pi - 0.01)
         out, npl, nmi = oracle_mod.wetting(n, ns, th)
-        if np.linalg.norm(np.cross(n, ns)) <= 1e-2:
-            assert np.array_equal(out, n)   # inside the no-rotation cone around +-n_s
-            continue
         assert abs(np.linalg.norm(npl) - 1) < 1e-12 and abs(np.linalg.norm(nmi) - 1) < 1e-12
         assert abs(npl @ ns - np.cos(th)) < 1e-12
         assert abs(nmi @ ns - np.cos(th)) < 1e-12
-        assert np.array_equal(out, npl)
-        # n+ lies in the plane of n and n_s, on the same side of n_s as n
+        # n+ lies in the plane of n and n_s, on the same side of n_s as n, and is the nearer one
         assert abs(np.cross(n, ns) @ npl) < 1e-12
-    # parallel or antiparallel n and n_s (to within 1e-2 rad): no plane to rotate in, n is kept
-    for n in ([0, 0, 1.0], [0, 0, -1.0], [1e-7, 0, -1.0], [9e-3, 0, 1.0]):
-        n = np.array(n) / np.linalg.norm(n)
-        out, _, _ = oracle_mod.wetting(n, np.array([0, 0, 1.0]), 1.0)
-        assert np.array_equal(out, n)
-    # just above the bound it realigns
-    n = np.array([1.1e-2, 0, 1.0]) / np.linalg.norm([1.1e-2, 0, 1.0])
-    out, _, _ = oracle_mod.wetting(n, np.array([0, 0, 1.0]), 1.0)
-    assert abs(out[2] - np.cos(1.0)) < 1e-9
+        assert np.linalg.norm(npl - n) <= np.linalg.norm(nmi - n)
+        if np.linalg.norm(np.cross(n, ns)) >= 1e-2:
+            assert np.array_equal(out, npl)
+
+
+def test_akai_cone_keeps_normal(oracle_mod):
+    """Within 1e-2 rad of +-n_s (no rotation plane) n is kept; just outside, n+ is used."""
+    ns = np.array([0.0, 0.0, 1.0])
+    th = np.deg2rad(60)
+    for sign in (1.0, -1.0):
+        for e in (0.0, 1e-12, 1e-6, 9.9e-3, 1.01e-2, 0.1):
+            n = np.array([e, 0.0, sign])
+            n /= np.linalg.norm(n)
+            out, npl, _ = oracle_mod.wetting(n, ns, th)
+            if np.linalg.norm(np.cross(n, ns)) < 1e-2:
+                assert np.array_equal(out, n)
+            else:
+                assert np.array_equal(out, npl)
+                assert abs(out @ ns - np.cos(th)) < 1e-12
 
 
 def _one_node(oracle_mod, fr, fp, **kw):
