@@ -135,6 +135,12 @@ lbm_status lbm_populations(lbm_ctx* ctx, void* d_fr, void* d_fp, void* d_g);
  * Either may be NULL. */
 lbm_status lbm_geometry(lbm_ctx* ctx, void* d_info, void* d_wet);
 
+/* Byte offsets inside a state snapshot of its three parts: the 19 colour-blind population
+ * planes (storage type, population-major), the 4 colour-scalar planes a, v_x, v_y, v_z (real
+ * type) and the 7 species planes (storage type; absent without species). In the *_DEV storages a
+ * population f is stored as (f - w_i) * 2^k (k = fp16_scale_log2 for FP16, 0 for BF16). */
+lbm_status lbm_state_layout(const lbm_params* params, size_t* f_off, size_t* a_off, size_t* g_off);
+
 /* Copies the current state (lbm_state_bytes) to / from caller device memory, stream-ordered.
  * Together with lbm_steps_done this is a bitwise-exact checkpoint. */
 lbm_status lbm_get_state(lbm_ctx* ctx, void* d_dst);
@@ -147,6 +153,31 @@ lbm_status lbm_set_state(lbm_ctx* ctx, const void* d_src, int64_t steps_done);
  * Errors: LBM_ERR_HIP if an event cannot be created or queried. */
 lbm_status lbm_set_profiling(lbm_ctx* ctx, int32_t enable);
 lbm_status lbm_kernel_times(lbm_ctx* ctx, double* kernel_ms, int64_t* steps);
+
+/* Discrete adjoint of the step, for gradients of the gas production L = m^p(T) - m^p(0)
+ * (eqs. product_mass, production_rate) with respect to the per-node contact angle theta(x)
+ * (eq. realigned_normal_vectors) and the reaction rate xi (eq. reactive_boundary_condition_*).
+ * An adjoint state holds 30 planes of N reals (context's real type), in the order of the state:
+ * 19 colour-blind populations, the colour fraction a, the three components of the recolouring
+ * vector v, 7 species populations. lbm_adjoint_bytes gives its size and the size of the scratch
+ * buffer lbm_adjoint_step needs (both caller-owned device memory). */
+lbm_status lbm_adjoint_bytes(const lbm_params* params, size_t* adj_bytes, size_t* scratch_bytes);
+
+/* Writes dL/dS_T for L = m^p(T) into d_adj, given the state d_state (lbm_state_bytes, as from
+ * lbm_get_state) of level T. Stream-ordered. */
+lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const void* d_state, void* d_adj);
+
+/* One reverse step: given the state S_t (d_state, device, lbm_state_bytes) and
+ * lambda_{t+1} = dL/dS_{t+1} (d_adj_in), writes lambda_t = dL/dS_t into d_adj_out (a different
+ * buffer) and adds (dS_{t+1}/dtheta)^T lambda_{t+1} to d_grad_theta (device, N doubles, nonzero
+ * only at wetting nodes) and (dS_{t+1}/dxi)^T lambda_{t+1} to *d_grad_xi (device, 1 double).
+ * d_scratch: device memory of the scratch size from lbm_adjoint_bytes. Uses the context's
+ * parameters and geometry and overwrites its per-step scratch fields (not its state). At the
+ * non-smooth points of the step (minimum in the reaction cap, gradient and wetting-cone
+ * guards) the derivative of the branch taken is used. Stream-ordered; errors: LBM_ERR_ARG for
+ * null or aliased buffers, LBM_ERR_HIP. */
+lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* d_state, const void* d_adj_in, void* d_adj_out,
+                            void* d_scratch, double* d_grad_theta, double* d_grad_xi);
 
 /* Number of steps taken since init (or the value given to lbm_set_state). */
 int64_t lbm_steps_done(const lbm_ctx* ctx);

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = [os.path.join(HERE, "csrc", "lbm.hip")]
-HEADERS = [os.path.join(HERE, "csrc", h) for h in ("lattice.hpp", "precision.hpp", "step_kernels.hpp")] + [
+HEADERS = [os.path.join(HERE, "csrc", h) for h in ("lattice.hpp", "precision.hpp", "step_kernels.hpp", "adjoint_kernels.hpp")] + [
     os.path.join(ROOT, "include", "lbm.h")]
 
 # Packed FP32 instructions are disabled for all device code.

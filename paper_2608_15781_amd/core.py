@@ -17,8 +17,9 @@ from . import build as _build
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 LBM_OK, LBM_ERR_ARG, LBM_ERR_ALLOC, LBM_ERR_HIP, LBM_ERR_NONFINITE, LBM_ERR_STATE, LBM_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 EXPORTED = ["lbm_version", "lbm_workspace_bytes", "lbm_state_bytes", "lbm_init", "lbm_step", "lbm_moments",
-            "lbm_populations", "lbm_geometry", "lbm_get_state", "lbm_set_state", "lbm_set_profiling",
-            "lbm_kernel_times", "lbm_steps_done", "lbm_free", "lbm_last_error"]
+            "lbm_populations", "lbm_geometry", "lbm_state_layout", "lbm_get_state", "lbm_set_state",
+            "lbm_set_profiling", "lbm_kernel_times", "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step",
+            "lbm_steps_done", "lbm_free", "lbm_last_error"]
 KERNELS = ("colour", "extrap", "normal", "collide")
 
 
@@ -67,6 +68,10 @@ def lib():
         L.lbm_geometry.argtypes = [vp, vp, vp]
         L.lbm_get_state.argtypes = [vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, i64]
+        L.lbm_state_layout.argtypes = [P(Params), P(sz), P(sz), P(sz)]
+        L.lbm_adjoint_bytes.argtypes = [P(Params), P(sz), P(sz)]
+        L.lbm_adjoint_seed.argtypes = [vp, vp, vp]
+        L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.lbm_set_profiling.argtypes = [vp, i32]
         L.lbm_kernel_times.argtypes = [vp, vp, vp]
         L.lbm_steps_done.argtypes = [vp]
@@ -224,6 +229,58 @@ class Lbm:
         self._check(lib().lbm_get_state(self._h, buf.data_ptr()), self._h)
         self.stream.synchronize()
         return buf
+
+    # ---- state layout and adjoint -------------------------------------------------------------
+    def state_layout(self):
+        """Byte offsets of the population, colour-scalar and species parts of a state snapshot."""
+        f, a, g = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(lib().lbm_state_layout(ctypes.byref(self.params), ctypes.byref(f), ctypes.byref(a),
+                                           ctypes.byref(g)), None)
+        return f.value, a.value, g.value
+
+    def state_parts(self, buf):
+        """Views (19, N), (4, N), (7, N) of a state snapshot (FP32/FP64 storage only)."""
+        t = self.torch
+        if self.precision not in (0, 1):
+            raise ValueError("state_parts needs FP32 or FP64 storage")
+        dt = self.real
+        es = 8 if self.precision == 0 else 4
+        f_off, a_off, g_off = self.state_layout()
+        N = self.N
+        f = buf[f_off:f_off + 19 * N * es].view(dt).view(19, N)
+        a = buf[a_off:a_off + 4 * N * es].view(dt).view(4, N)
+        g = buf[g_off:g_off + 7 * N * es].view(dt).view(7, N) if self.params.species else None
+        return f, a, g
+
+    def adjoint_bytes(self):
+        ab, sb = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(lib().lbm_adjoint_bytes(ctypes.byref(self.params), ctypes.byref(ab), ctypes.byref(sb)), None)
+        return ab.value, sb.value
+
+    def new_adjoint(self):
+        """A zeroed adjoint state: (30, N) tensor of the context's real type."""
+        return self.torch.zeros(30, self.N, dtype=self.real, device=self.device)
+
+    def new_scratch(self):
+        return self.torch.empty(self.adjoint_bytes()[1] + 256, dtype=self.torch.uint8, device=self.device)
+
+    @staticmethod
+    def _aligned(t):
+        p = t.data_ptr()
+        return p + ((-p) % 256)
+
+    def adjoint_seed(self, state, adj):
+        """adj <- dL/dS_T of L = m^p(T) at the state snapshot `state`."""
+        self._check(lib().lbm_adjoint_seed(self._h, state.data_ptr(), adj.data_ptr()), self._h)
+
+    def adjoint_step(self, state, adj_in, adj_out, scratch, grad_theta, grad_xi):
+        """adj_out <- (dS_{t+1}/dS_t)^T adj_in at the state S_t; accumulates grad_theta (N doubles) and
+        grad_xi (1 double) on the device."""
+        if grad_theta.dtype != self.torch.float64 or grad_xi.dtype != self.torch.float64:
+            raise ValueError("gradients accumulate in float64")
+        self._check(lib().lbm_adjoint_step(self._h, state.data_ptr(), adj_in.data_ptr(), adj_out.data_ptr(),
+                                           ctypes.c_void_p(self._aligned(scratch)), grad_theta.data_ptr(),
+                                           grad_xi.data_ptr()), self._h)
 
     def set_profiling(self, enable: bool):
         self._check(lib().lbm_set_profiling(self._h, int(bool(enable))), self._h)

@@ -1,0 +1,610 @@
+// Discrete adjoint of one time step (reverse mode, HIP, gfx950).
+//
+// For the step map S_{t+1} = Phi(S_t; theta, xi) of step_kernels.hpp, one adjoint step turns
+// lambda_{t+1} = dL/dS_{t+1} into lambda_t = (dPhi/dS_t)^T lambda_{t+1} and accumulates
+// (dPhi/dtheta)^T lambda_{t+1} per node and (dPhi/dxi)^T lambda_{t+1}. The forward fields of
+// level t (rho^N, rho^m, n*, |G|) are first recomputed from S_t by the forward colour,
+// extrapolation and normal kernels; the reverse pass then runs
+//   k_adj_collide   reverse of the collide kernel at each fluid node; the pull transposes to a
+//                   scatter that is a bijection on (node, direction), so every adjoint population
+//                   is written exactly once, without atomics
+//   k_adj_normal    curvature transpose (gather of the neighbours' dH/dn*), then the normal and
+//                   Akai realignment reversed to d/dG; accumulates dL/dtheta
+//   k_adj_grad      transpose of the isotropic gradient stencil (gather), fluid and solid nodes
+//   k_adj_colour    transpose of the colour extrapolation into solids, then d rho^N -> d rho^r, d rho^m
+//   k_adj_final     the colour pass's dependence on f^m, a and v of each pull source (gather)
+// Non-smooth points (the minimum in the reaction cap, the |G| and wetting-cone guards) take the
+// derivative of the branch the forward step took. Gradients are accumulated in FP64.
+#pragma once
+
+#include "step_kernels.hpp"
+
+namespace lbm {
+
+// Adjoint-state layout: 30 planes of N reals, same order as the state (19 f^m, a, v_x, v_y,
+// v_z, 7 species).
+constexpr int kAdjPlanes = 30;
+constexpr int kAdjA = 19, kAdjV = 20, kAdjG = 23;
+
+template <class R>
+struct AdjArgs {
+  const R* lin;      // lambda_{t+1}
+  R* lout;           // lambda_t
+  R* lrn;            // d/d rho^N: collide part, then total (fluid and extrapolated solid nodes)
+  R* lnc;            // 3 planes: d/d n* from the collide (including its own curvature terms)
+  R* lglen;          // d/d |G|
+  R* lH;             // d/d H
+  R* lG;             // 3 planes: d/d G
+  R* lrr;            // d/d rho^r of the colour pass
+  R* lrm;            // d/d rho^m of the colour pass
+  R* lgo;            // species outflow nodes: d/d S_1(x) through their own pull
+  const R* rmv;      // rho^m of level t (forward recompute)
+  double* gtheta;    // dL/dtheta per node (accumulated)
+  double* partials;  // dL/dxi per workgroup (5 planes of workgroup sums, slot 0 used)
+};
+
+// Forward-mode dual with one derivative, used to take the vector-Jacobian product of the
+// closed-form back transform eight times (one seed per input).
+template <class R>
+struct Dl {
+  R v, d;
+  __device__ Dl() {}
+  __device__ Dl(double x) : v(R(x)), d(R(0)) {}
+  __device__ Dl(R x, R dx) : v(x), d(dx) {}
+};
+template <class R> __device__ inline Dl<R> operator+(Dl<R> a, Dl<R> b) { return Dl<R>(a.v + b.v, a.d + b.d); }
+template <class R> __device__ inline Dl<R> operator-(Dl<R> a, Dl<R> b) { return Dl<R>(a.v - b.v, a.d - b.d); }
+template <class R> __device__ inline Dl<R> operator-(Dl<R> a) { return Dl<R>(-a.v, -a.d); }
+template <class R> __device__ inline Dl<R> operator*(Dl<R> a, Dl<R> b) { return Dl<R>(a.v * b.v, a.d * b.v + a.v * b.d); }
+
+// (d/d(ux,uy,uz,k5..k9)) of sum_i ld_i d_i(u, k).
+template <class R>
+__device__ inline void cm_back_vjp(const R in[8], const R ld[19], R out[8]) {
+#pragma unroll 1
+  for (int s = 0; s < 8; ++s) {
+    Dl<R> x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = Dl<R>(in[j], j == s ? R(1) : R(0));
+    Dl<R> d[19];
+    cm_back(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], d);
+    R acc = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) acc += ld[i] * d[i].d;
+    out[s] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Seed for L = m^p(T) = sum over fluid nodes and directions of the product populations of S_T:
+// sum_i S^p_i = (1 - a) sum_i f^m_i (the v term cancels by lattice symmetry).
+// ---------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adj_seed(StepArgs<P> A, typename Prec<P>::R* lout) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  if (t >= A.nfluid) return;
+  const int n = A.fluid[t];
+  const size_t N = A.N;
+  const R a = A.ain[n];
+  R s = 0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    s += Prec<P>::ld(A.fin[size_t(i) * N + n], R(D::w(i)), A.inv_scale);
+    lout[size_t(i) * N + n] = R(1) - a;
+  }
+  lout[size_t(kAdjA) * N + n] = -s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Reverse of the collide kernel at one fluid node (forward arithmetic recomputed as in k_collide).
+// ---------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  double gxi = 0.0;
+  const int n = (t < A.nfluid) ? A.fluid[t] : 0;
+  const uint32_t inf = (t < A.nfluid) ? A.info[n] : 0u;
+  if (inf & kFluid) {
+    const Nbr nb = make_nbr(n, A.geo);
+    const size_t N = A.N;
+    // ---------------- forward recompute ----------------
+    R f[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const bool bb = (i < 18) && ((inf >> i) & 1u);
+      const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+      const int q = bb ? D::opp[i] : i;
+      f[i] = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
+    }
+    R rm = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) rm += f[i];
+    R mx = 0, my = 0, mz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      if (D::cx[i]) { mx += R(D::cx[i]) * f[i]; pxx += f[i]; }
+      if (D::cy[i]) { my += R(D::cy[i]) * f[i]; pyy += f[i]; }
+      if (D::cz[i]) { mz += R(D::cz[i]) * f[i]; pzz += f[i]; }
+      if (D::cx[i] && D::cy[i]) pxy += R(D::cx[i] * D::cy[i]) * f[i];
+      if (D::cx[i] && D::cz[i]) pxz += R(D::cx[i] * D::cz[i]) * f[i];
+      if (D::cy[i] && D::cz[i]) pyz += R(D::cy[i] * D::cz[i]) * f[i];
+    }
+    const R irm = R(1) / rm;
+    const R ux = mx * irm, uy = my * irm, uz = mz * irm;
+    const R rn = A.rhoN[n];
+    const R rr = R(0.5) * rm * (R(1) + rn);
+    const R rp = R(0.5) * rm * (R(1) - rn);
+    const R nn[3] = {A.nst[n], A.nst[N + n], A.nst[2 * N + n]};
+    const R glen = A.nst[3 * N + n];
+    const bool has_n = glen > A.eps;
+    R H = 0;
+    R Jm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if (has_n) {
+#pragma unroll
+      for (int i = 0; i < 18; ++i) {
+        const bool sol = (inf >> D::opp[i]) & 1u;
+        const int m = nb.at(D::cx[i], D::cy[i], D::cz[i]);
+        const R a0 = sol ? nn[0] : A.nst[m];
+        const R a1 = sol ? nn[1] : A.nst[N + m];
+        const R a2 = sol ? nn[2] : A.nst[2 * N + m];
+        const R w3 = R(3.0 * D::w(i));
+        if (D::cx[i]) { Jm[0][0] += w3 * R(D::cx[i]) * a0; Jm[1][0] += w3 * R(D::cx[i]) * a1; Jm[2][0] += w3 * R(D::cx[i]) * a2; }
+        if (D::cy[i]) { Jm[0][1] += w3 * R(D::cy[i]) * a0; Jm[1][1] += w3 * R(D::cy[i]) * a1; Jm[2][1] += w3 * R(D::cy[i]) * a2; }
+        if (D::cz[i]) { Jm[0][2] += w3 * R(D::cz[i]) * a0; Jm[1][2] += w3 * R(D::cz[i]) * a1; Jm[2][2] += w3 * R(D::cz[i]) * a2; }
+      }
+      R nJn = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) nJn += nn[a] * nn[b] * Jm[a][b];
+      H = -((Jm[0][0] + Jm[1][1] + Jm[2][2]) - nJn);
+    }
+    const R fc = R(0.5) * A.sigma * H * glen * irm;
+    R dur[3], dup[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { dur[a] = fc * nn[a] + A.acc[0][a]; dup[a] = fc * nn[a] + A.acc[1][a]; }
+    const R up[3] = {ux + R(0.5) * (rr * dur[0] + rp * dup[0]) * irm, uy + R(0.5) * (rr * dur[1] + rp * dup[1]) * irm,
+                     uz + R(0.5) * (rr * dur[2] + rp * dup[2]) * irm};
+    R g[7] = {0, 0, 0, 0, 0, 0, 0};
+    R C = R(1);
+    const bool inlet = A.species && (inf & kInlet);
+    const bool outlet = A.species && (inf & kOutlet);
+    if (A.species) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        if (i == 1 && outlet) {
+          g[i] = Prec<P>::ld(A.gin[N + n], R(D3Q7::w(1)), A.inv_gscale);
+        } else {
+          const bool bb = (inf >> i) & 1u;
+          const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+          const int q = bb ? D3Q7::opp[i] : i;
+          g[i] = Prec<P>::ld(A.gin[size_t(q) * N + src], R(D3Q7::w(i)), A.inv_gscale);
+        }
+      }
+      g[6] = Prec<P>::ld(A.gin[6 * N + n], R(D3Q7::w(6)), A.inv_gscale);
+      C = 0;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) C += g[i];
+      if (inlet) C = A.c_in;
+    }
+    const R Ur[3] = {ux + dur[0], uy + dur[1], uz + dur[2]};
+    const R Upv[3] = {ux + dup[0], uy + dup[1], uz + dup[2]};
+    const int rnn = int((inf & kRnnMask) >> kRnnShift);
+    R delta = 0;
+    int branch = 0;  // 0: no reaction, 1: rate, 2: cap = rho^r, 3: cap = C, 4: paper rate, 5: paper full
+    if (rnn > 0 && rr > R(0)) {
+      if (A.species) {
+        if (C > R(0)) {
+          const R rate = A.xi * R(rnn) * rr * C;
+          const R cap = fmin(rr, C);
+          delta = fmin(rate, cap);
+          branch = (rate < cap) ? 1 : (rr < C ? 2 : 3);
+        }
+      } else {
+        const R frac = A.xi * R(rnn);
+        delta = fmin(frac, R(1)) * rr;
+        branch = (frac < R(1)) ? 4 : 5;
+      }
+    }
+    const bool reacts = delta != R(0);
+    const R keep = reacts ? R(1) - delta / rr : R(1);
+    const R vc = keep * A.beta * rr * rp * irm;
+
+    // ---------------- reverse ----------------
+    R lf[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) lf[i] = J.lin[size_t(i) * N + n];
+    const R la = J.lin[size_t(kAdjA) * N + n];
+    const R lv[3] = {J.lin[size_t(kAdjV) * N + n], J.lin[size_t(kAdjV + 1) * N + n], J.lin[size_t(kAdjV + 2) * N + n]};
+    R l_C = 0, l_delta = 0, l_up[3] = {0, 0, 0};
+    R l_g[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (A.species) {
+      const R sink = reacts ? R(1) - delta / C : R(1);
+      R l_sink = 0;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        const R cu = (i == 0) ? up[0] : (i == 1) ? -up[0] : (i == 2) ? up[1] : (i == 3) ? -up[1] : (i == 4) ? up[2] : (i == 5) ? -up[2] : R(0);
+        const R wc = R(D3Q7::w(i));
+        const R geq = wc * C * (R(1) + R(4) * cu);
+        const R gi = inlet ? geq : g[i];
+        const R pre = gi + (geq - gi) * A.inv_tau_c;
+        const R lgo = J.lin[size_t(kAdjG + i) * N + n];
+        const R l_pre = lgo * sink;
+        l_sink += lgo * pre;
+        R l_geq = l_pre * A.inv_tau_c;
+        const R l_gi = l_pre * (R(1) - A.inv_tau_c);
+        if (inlet) l_geq += l_gi;
+        else l_g[i] = l_gi;
+        l_C += l_geq * wc * (R(1) + R(4) * cu);
+        const R l_cu = l_geq * wc * C * R(4);
+        if (i == 0) l_up[0] += l_cu;
+        if (i == 1) l_up[0] -= l_cu;
+        if (i == 2) l_up[1] += l_cu;
+        if (i == 3) l_up[1] -= l_cu;
+        if (i == 4) l_up[2] += l_cu;
+        if (i == 5) l_up[2] -= l_cu;
+      }
+      if (reacts) {
+        l_delta += -l_sink / C;
+        l_C += l_sink * delta / (C * C);
+      }
+    }
+    // a = keep rho^r / rho^m; v = vc n* with vc = keep beta rho^r rho^p / rho^m.
+    R l_keep = la * rr * irm, l_rr = la * keep * irm, l_rp = 0, l_rm = -la * keep * rr * irm * irm;
+    R l_n[3] = {0, 0, 0};
+    if (has_n) {
+      const R l_vc = lv[0] * nn[0] + lv[1] * nn[1] + lv[2] * nn[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) l_n[a] += vc * lv[a];
+      l_keep += l_vc * A.beta * rr * rp * irm;
+      l_rr += l_vc * keep * A.beta * rp * irm;
+      l_rp += l_vc * keep * A.beta * rr * irm;
+      l_rm += -l_vc * vc * irm;
+    }
+    if (reacts) {
+      l_delta += -l_keep / rr;
+      l_rr += l_keep * delta / (rr * rr);
+    }
+    switch (branch) {
+      case 1:
+        gxi += double(l_delta * R(rnn) * rr * C);
+        l_rr += l_delta * A.xi * R(rnn) * C;
+        l_C += l_delta * A.xi * R(rnn) * rr;
+        break;
+      case 2: l_rr += l_delta; break;
+      case 3: l_C += l_delta; break;
+      case 4:
+        gxi += double(l_delta * R(rnn) * rr);
+        l_rr += l_delta * A.xi * R(rnn);
+        break;
+      case 5: l_rr += l_delta; break;
+      default: break;
+    }
+    // f^{m,*}_i = w_i (base + 3 c.M + 4.5 c.Pi.c) + d_i
+    R l_base = 0, l_M[3] = {0, 0, 0}, l_Pxx = 0, l_Pyy = 0, l_Pzz = 0, l_Pxy = 0, l_Pxz = 0, l_Pyz = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const int cx = D::cx[i], cy = D::cy[i], cz = D::cz[i];
+      const R wl = R(D::w(i)) * lf[i];
+      l_base += wl;
+      if (cx) { l_M[0] += R(3 * cx) * wl; l_Pxx += R(4.5) * wl; }
+      if (cy) { l_M[1] += R(3 * cy) * wl; l_Pyy += R(4.5) * wl; }
+      if (cz) { l_M[2] += R(3 * cz) * wl; l_Pzz += R(4.5) * wl; }
+      if (cx && cy) l_Pxy += R(9 * cx * cy) * wl;
+      if (cx && cz) l_Pxz += R(9 * cx * cz) * wl;
+      if (cy && cz) l_Pyz += R(9 * cy * cz) * wl;
+    }
+    l_rm += l_base;
+    l_Pxx += R(-1.5) * l_base;
+    l_Pyy += R(-1.5) * l_base;
+    l_Pzz += R(-1.5) * l_base;
+    l_rr += l_M[0] * Ur[0] + l_M[1] * Ur[1] + l_M[2] * Ur[2];
+    l_rp += l_M[0] * Upv[0] + l_M[1] * Upv[1] + l_M[2] * Upv[2];
+    l_rr += l_Pxx * Ur[0] * Ur[0] + l_Pyy * Ur[1] * Ur[1] + l_Pzz * Ur[2] * Ur[2] + l_Pxy * Ur[0] * Ur[1] +
+            l_Pxz * Ur[0] * Ur[2] + l_Pyz * Ur[1] * Ur[2];
+    l_rp += l_Pxx * Upv[0] * Upv[0] + l_Pyy * Upv[1] * Upv[1] + l_Pzz * Upv[2] * Upv[2] + l_Pxy * Upv[0] * Upv[1] +
+            l_Pxz * Upv[0] * Upv[2] + l_Pyz * Upv[1] * Upv[2];
+    R l_Ur[3], l_Up[3];
+    l_Ur[0] = rr * (l_M[0] + R(2) * l_Pxx * Ur[0] + l_Pxy * Ur[1] + l_Pxz * Ur[2]);
+    l_Ur[1] = rr * (l_M[1] + R(2) * l_Pyy * Ur[1] + l_Pxy * Ur[0] + l_Pyz * Ur[2]);
+    l_Ur[2] = rr * (l_M[2] + R(2) * l_Pzz * Ur[2] + l_Pxz * Ur[0] + l_Pyz * Ur[1]);
+    l_Up[0] = rp * (l_M[0] + R(2) * l_Pxx * Upv[0] + l_Pxy * Upv[1] + l_Pxz * Upv[2]);
+    l_Up[1] = rp * (l_M[1] + R(2) * l_Pyy * Upv[1] + l_Pxy * Upv[0] + l_Pyz * Upv[2]);
+    l_Up[2] = rp * (l_M[2] + R(2) * l_Pzz * Upv[2] + l_Pxz * Upv[0] + l_Pyz * Upv[1]);
+    R l_u[3], l_dur[3], l_dup[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { l_u[a] = l_Ur[a] + l_Up[a]; l_dur[a] = l_Ur[a]; l_dup[a] = l_Up[a]; }
+    // T^{-1} k* and the relaxed central moments.
+    const R cxx = pxx - rm * ux * ux, cyy = pyy - rm * uy * uy, czz = pzz - rm * uz * uz;
+    const R kin[8] = {ux, uy, uz, A.relax * (cxx - cyy), A.relax * (cyy - czz), A.relax * (pxy - rm * ux * uy),
+                      A.relax * (pxz - rm * ux * uz), A.relax * (pyz - rm * uy * uz)};
+    R kv[8];
+    cm_back_vjp(kin, lf, kv);
+    l_u[0] += kv[0];
+    l_u[1] += kv[1];
+    l_u[2] += kv[2];
+    const R l_cxx = A.relax * kv[3], l_cyy = A.relax * (kv[4] - kv[3]), l_czz = -A.relax * kv[4];
+    const R l_c7 = A.relax * kv[5], l_c8 = A.relax * kv[6], l_c9 = A.relax * kv[7];
+    const R l_pxx = l_cxx, l_pyy = l_cyy, l_pzz = l_czz, l_pxy = l_c7, l_pxz = l_c8, l_pyz = l_c9;
+    l_rm += -(l_cxx * ux * ux + l_cyy * uy * uy + l_czz * uz * uz + l_c7 * ux * uy + l_c8 * ux * uz + l_c9 * uy * uz);
+    l_u[0] += -rm * (R(2) * l_cxx * ux + l_c7 * uy + l_c8 * uz);
+    l_u[1] += -rm * (R(2) * l_cyy * uy + l_c7 * ux + l_c9 * uz);
+    l_u[2] += -rm * (R(2) * l_czz * uz + l_c8 * ux + l_c9 * uy);
+    // u_phys = u + (rr du^r + rp du^p) / (2 rm)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      l_u[a] += l_up[a];
+      l_rr += R(0.5) * l_up[a] * dur[a] * irm;
+      l_rp += R(0.5) * l_up[a] * dup[a] * irm;
+      l_dur[a] += R(0.5) * rr * irm * l_up[a];
+      l_dup[a] += R(0.5) * rp * irm * l_up[a];
+      l_rm += -R(0.5) * l_up[a] * (rr * dur[a] + rp * dup[a]) * irm * irm;
+    }
+    // du^k = fc n* + a^k,  fc = sigma H |G| / (2 rm)
+    R l_fc = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      l_fc += (l_dur[a] + l_dup[a]) * nn[a];
+      l_n[a] += fc * (l_dur[a] + l_dup[a]);
+    }
+    const R l_H = l_fc * R(0.5) * A.sigma * glen * irm;
+    const R l_glen = l_fc * R(0.5) * A.sigma * H * irm;
+    l_rm += -l_fc * fc * irm;
+    if (has_n) {
+      // H = -(tr J - n.J.n): dependence on the centre normal, including solid neighbours' copies.
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        R s = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) s += nn[b] * (Jm[a][b] + Jm[b][a]);
+        l_n[a] += l_H * s;
+      }
+#pragma unroll
+      for (int i = 0; i < 18; ++i) {
+        if ((inf >> D::opp[i]) & 1u) {
+          const R cn = R(D::cx[i]) * nn[0] + R(D::cy[i]) * nn[1] + R(D::cz[i]) * nn[2];
+          const R w3 = R(-3.0 * D::w(i)) * l_H;
+          l_n[0] += w3 * (R(D::cx[i]) - nn[0] * cn);
+          l_n[1] += w3 * (R(D::cy[i]) - nn[1] * cn);
+          l_n[2] += w3 * (R(D::cz[i]) - nn[2] * cn);
+        }
+      }
+    }
+    // u = m / rm
+    R l_m[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) l_m[a] = l_u[a] * irm;
+    l_rm += -(l_u[0] * ux + l_u[1] * uy + l_u[2] * uz) * irm;
+    // rho^r, rho^p from rho^m and rho^N
+    l_rm += R(0.5) * (R(1) + rn) * l_rr + R(0.5) * (R(1) - rn) * l_rp;
+    const R l_rn = R(0.5) * rm * (l_rr - l_rp);
+    if (A.species && !inlet)
+#pragma unroll
+      for (int i = 0; i < 7; ++i) l_g[i] += l_C;
+    // pulled populations: rm = sum f, m = sum f c, second moments
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const int cx = D::cx[i], cy = D::cy[i], cz = D::cz[i];
+      R v = l_rm;
+      if (cx) v += R(cx) * l_m[0] + l_pxx;
+      if (cy) v += R(cy) * l_m[1] + l_pyy;
+      if (cz) v += R(cz) * l_m[2] + l_pzz;
+      if (cx && cy) v += R(cx * cy) * l_pxy;
+      if (cx && cz) v += R(cx * cz) * l_pxz;
+      if (cy && cz) v += R(cy * cz) * l_pyz;
+      // transpose of the pull: the population S_q(src) read by this node as direction i
+      const bool bb = (i < 18) && ((inf >> i) & 1u);
+      const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+      const int q = bb ? D::opp[i] : i;
+      J.lout[size_t(q) * N + src] = v;
+    }
+    if (A.species) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        if (i == 1 && outlet) {
+          J.lgo[n] = l_g[1];
+        } else {
+          const bool bb = (inf >> i) & 1u;
+          const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+          const int q = bb ? D3Q7::opp[i] : i;
+          J.lout[size_t(kAdjG + q) * N + src] = l_g[i];
+        }
+      }
+      J.lout[size_t(kAdjG + 6) * N + n] = l_g[6];
+    }
+    J.lrn[n] = l_rn;
+    J.lnc[n] = l_n[0];
+    J.lnc[N + n] = l_n[1];
+    J.lnc[2 * N + n] = l_n[2];
+    J.lglen[n] = l_glen;
+    J.lH[n] = has_n ? l_H : R(0);
+  }
+  double s5[5] = {gxi, 0, 0, 0, 0};
+  block_reduce5(s5, J.partials);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Curvature transpose and the normal / wetting reverse at each fluid node.
+// ---------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  if (t >= A.nfluid) return;
+  const int n = A.fluid[t];
+  const uint32_t inf = A.info[n];
+  const Nbr nb = make_nbr(n, A.geo);
+  const size_t N = A.N;
+  R mu[3] = {J.lnc[n], J.lnc[N + n], J.lnc[2 * N + n]};
+  // H(x) at each fluid neighbour x = y - c_i used n*(x + c_i) = n*(y):
+  // dH(x)/dn*_a(y) = -3 w_i (c_ia - n_a(x) (n(x).c_i)).
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    if ((inf >> i) & 1u) continue;  // y - c_i is solid
+    const int m = nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+    const R lh = J.lH[m];
+    if (lh == R(0)) continue;
+    const R q0 = A.nst[m], q1 = A.nst[N + m], q2 = A.nst[2 * N + m];
+    const R cn = R(D::cx[i]) * q0 + R(D::cy[i]) * q1 + R(D::cz[i]) * q2;
+    const R w3 = R(-3.0 * D::w(i)) * lh;
+    mu[0] += w3 * (R(D::cx[i]) - q0 * cn);
+    mu[1] += w3 * (R(D::cy[i]) - q1 * cn);
+    mu[2] += w3 * (R(D::cz[i]) - q2 * cn);
+  }
+  // Recompute the raw gradient and the normal of this node (as k_normal).
+  R g[3] = {0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const int p = D::half[j];
+    const R d = A.rhoN[nb.at(D::cx[p], D::cy[p], D::cz[p])] - A.rhoN[nb.at(-D::cx[p], -D::cy[p], -D::cz[p])];
+    const R c3w = R(3.0 * D::w(p));
+    if (D::cx[p]) g[0] += c3w * R(D::cx[p]) * d;
+    if (D::cy[p]) g[1] += c3w * R(D::cy[p]) * d;
+    if (D::cz[p]) g[2] += c3w * R(D::cz[p]) * d;
+  }
+  const R len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  R lG[3] = {0, 0, 0};
+  if (len > A.eps) {
+    const R il = R(1) / len;
+    const R nv[3] = {g[0] * il, g[1] * il, g[2] * il};
+    R ln[3] = {mu[0], mu[1], mu[2]};
+    if (inf & kWet) {
+      const R sx = A.wet[n], sy = A.wet[N + n], sz = A.wet[2 * N + n];
+      if (sx * sx + sy * sy + sz * sz > R(0.5)) {
+        const R ct = A.wet[3 * N + n];
+        const R st = sqrt(fmax(R(0), (R(1) - ct) * (R(1) + ct)));
+        const R cp = sx * nv[0] + sy * nv[1] + sz * nv[2];
+        const R c0 = nv[1] * sz - nv[2] * sy, c1 = nv[2] * sx - nv[0] * sz, c2 = nv[0] * sy - nv[1] * sx;
+        const R sp = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+        if (sp >= R(1e-2)) {
+          // n* = a n_s + b n, b = sin(theta)/sin(theta'), a = cos(theta) - b cos(theta')
+          const R b = st / sp;
+          const R ns[3] = {sx, sy, sz};
+          const R tv[3] = {(nv[0] - cp * sx) / sp, (nv[1] - cp * sy) / sp, (nv[2] - cp * sz) / sp};
+          const R mns = mu[0] * sx + mu[1] * sy + mu[2] * sz;
+          const R mn = mu[0] * nv[0] + mu[1] * nv[1] + mu[2] * nv[2];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) ln[a] = b * mu[a] + mns * (b * cp / sp * tv[a] - b * ns[a]) - mn * (b / sp) * tv[a];
+          // d n*/d theta = (-sin(theta) - cos(theta) cos(theta')/sin(theta')) n_s + (cos(theta)/sin(theta')) n
+          J.gtheta[n] += double(mns * (-st - ct * cp / sp) + mn * (ct / sp));
+        }
+      }
+    }
+    const R lnn = ln[0] * nv[0] + ln[1] * nv[1] + ln[2] * nv[2];
+    const R lgl = J.lglen[n];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) lG[a] = (ln[a] - lnn * nv[a]) * il + lgl * nv[a];
+  }
+  J.lG[n] = lG[0];
+  J.lG[N + n] = lG[1];
+  J.lG[2 * N + n] = lG[2];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Transpose of G(x) = 3 sum_i w_i c_i rho^N(x + c_i): d/d rho^N(y) gathers 3 w_i c_i . lG(y - c_i)
+// over fluid nodes y - c_i. EXT: y is a solid node with extrapolated colour (otherwise fluid, and
+// the collide part of d/d rho^N is added).
+// ---------------------------------------------------------------------------------------------
+template <int P, bool EXT>
+__global__ __launch_bounds__(kBlock) void k_adj_grad(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  if (t >= (EXT ? A.next : A.nfluid)) return;
+  const int n = EXT ? A.ext[t] : A.fluid[t];
+  const uint32_t inf = A.info[n];
+  const Nbr nb = make_nbr(n, A.geo);
+  const size_t N = A.N;
+  R s = 0;
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    // fluid y: bit i set means y - c_i is solid; solid y: bit opp(i) set means y - c_i is fluid
+    const bool src_fluid = EXT ? ((inf >> D::opp[i]) & 1u) : !((inf >> i) & 1u);
+    if (!src_fluid) continue;
+    const int m = nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+    R v = 0;
+    if (D::cx[i]) v += R(D::cx[i]) * J.lG[m];
+    if (D::cy[i]) v += R(D::cy[i]) * J.lG[N + m];
+    if (D::cz[i]) v += R(D::cz[i]) * J.lG[2 * N + m];
+    s += R(3.0 * D::w(i)) * v;
+  }
+  J.lrn[n] = EXT ? s : J.lrn[n] + s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Transpose of the extrapolation rho^N(y) = sum_j w_j rho^N(y + c_j) / den(y) into the fluid node
+// z = y + c_j, then rho^N = (2 rho^r - rho^m)/rho^m reversed to d/d rho^r and d/d rho^m.
+// ---------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adj_colour(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  if (t >= A.nfluid) return;
+  const int n = A.fluid[t];
+  const uint32_t inf = A.info[n];
+  const Nbr nb = make_nbr(n, A.geo);
+  R l = J.lrn[n];
+#pragma unroll
+  for (int j = 0; j < 18; ++j) {
+    if (!((inf >> j) & 1u)) continue;  // z - c_j is fluid
+    const int y = nb.at(-D::cx[j], -D::cy[j], -D::cz[j]);
+    const uint32_t iy = A.info[y];
+    R den = 0;
+#pragma unroll
+    for (int k = 0; k < 18; ++k)
+      if ((iy >> k) & 1u) den += R(D::w(k));
+    l += R(D::w(j)) / den * J.lrn[y];
+  }
+  const R rm = J.rmv[n];
+  const R rn = A.rhoN[n];
+  J.lrr[n] = R(2) * l / rm;
+  J.lrm[n] = -(R(1) + rn) * l / rm;
+}
+
+// ---------------------------------------------------------------------------------------------
+// The colour pass read f^m_q, a and v of each pull source: add those terms to lambda_t at the
+// source y. The reader of S_q(y) is y + c_q if that node is fluid, else y itself (bounce-back),
+// and y itself for the rest population.
+// ---------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adj_final(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  if (t >= A.nfluid) return;
+  const int n = A.fluid[t];
+  const uint32_t inf = A.info[n];
+  const Nbr nb = make_nbr(n, A.geo);
+  const size_t N = A.N;
+  const R a = A.ain[n];
+  R la = 0, lv[3] = {0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const bool self = (q == 18) || ((inf >> D::opp[q]) & 1u);  // y + c_q solid: bounce-back reader
+    const int rd = self ? n : nb.at(D::cx[q], D::cy[q], D::cz[q]);
+    const R lr = J.lrr[rd], lm = J.lrm[rd];
+    const R fq = Prec<P>::ld(A.fin[size_t(q) * N + n], R(D::w(q)), A.inv_scale);
+    J.lout[size_t(q) * N + n] += lr * a + lm;
+    la += lr * fq;
+    const R wl = R(D::w_over_len(q)) * lr;
+    lv[0] += wl * R(D::cx[q]);
+    lv[1] += wl * R(D::cy[q]);
+    lv[2] += wl * R(D::cz[q]);
+  }
+  J.lout[size_t(kAdjA) * N + n] = la;
+  J.lout[size_t(kAdjV) * N + n] = lv[0];
+  J.lout[size_t(kAdjV + 1) * N + n] = lv[1];
+  J.lout[size_t(kAdjV + 2) * N + n] = lv[2];
+  if (A.species && (inf & kOutlet)) J.lout[size_t(kAdjG + 1) * N + n] += J.lgo[n];
+}
+
+__global__ void k_add_scalar(const double* src, double* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst += *src;
+}
+
+}  // namespace lbm

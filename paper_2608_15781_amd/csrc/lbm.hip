@@ -14,6 +14,7 @@
 #include "lattice.hpp"
 #include "precision.hpp"
 #include "step_kernels.hpp"
+#include "adjoint_kernels.hpp"
 
 using namespace lbm;
 
@@ -58,6 +59,32 @@ Layout make_layout(const lbm_params& p) {
   L.counts = o; o = align_up(o + 4 * (size_t(nb) + 2));
   L.total = o;
   return L;
+}
+
+struct AdjLayout {
+  size_t adj_bytes;                                                       // one adjoint state
+  size_t lrn, lnc, lglen, lH, lG, lrr, lrm, lgo, rmv, partials, sum, total;  // scratch offsets
+};
+
+AdjLayout make_adj_layout(const lbm_params& p) {
+  AdjLayout A{};
+  const size_t N = size_t(p.nx) * p.ny * p.nz;
+  const size_t r = real_bytes(p.precision);
+  A.adj_bytes = align_up(size_t(kAdjPlanes) * r * N);
+  size_t o = 0;
+  A.lrn = o; o = align_up(o + r * N);
+  A.lnc = o; o = align_up(o + 3 * r * N);
+  A.lglen = o; o = align_up(o + r * N);
+  A.lH = o; o = align_up(o + r * N);
+  A.lG = o; o = align_up(o + 3 * r * N);
+  A.lrr = o; o = align_up(o + r * N);
+  A.lrm = o; o = align_up(o + r * N);
+  A.lgo = o; o = align_up(o + r * N);
+  A.rmv = o; o = align_up(o + r * N);
+  A.partials = o; o = align_up(o + 5 * sizeof(double) * size_t(make_layout(p).nblocks));
+  A.sum = o; o = align_up(o + 5 * sizeof(double));
+  A.total = o;
+  return A;
 }
 
 }  // namespace
@@ -414,6 +441,77 @@ lbm_status launch_init(lbm_ctx* c, const uint8_t* d_solid, const uint8_t* d_reac
   return LBM_OK;
 }
 
+template <int P>
+StepArgs<P> make_args_from(lbm_ctx* c, const void* state) {
+  using S = typename Prec<P>::S;
+  using R = typename Prec<P>::R;
+  StepArgs<P> A = make_args<P>(c, c->cur);
+  const char* sb = static_cast<const char*>(state);
+  A.fin = reinterpret_cast<const S*>(sb + c->L.f_off);
+  A.ain = reinterpret_cast<const R*>(sb + c->L.a_off);
+  A.gin = reinterpret_cast<const S*>(sb + c->L.g_off);
+  A.fout = nullptr;
+  A.aout = nullptr;
+  A.gout = nullptr;
+  return A;
+}
+
+template <int P>
+lbm_status launch_adj_seed(lbm_ctx* c, const void* state, void* adj) {
+  using R = typename Prec<P>::R;
+  StepArgs<P> A = make_args_from<P>(c, state);
+  const AdjLayout AL = make_adj_layout(c->p);
+  HIP_TRY(c, hipMemsetAsync(adj, 0, AL.adj_bytes, c->stream));
+  if (c->nb_fluid)
+    hipLaunchKernelGGL(k_adj_seed<P>, dim3(c->nb_fluid), dim3(kBlock), 0, c->stream, A, static_cast<R*>(adj));
+  HIP_TRY(c, hipGetLastError());
+  return LBM_OK;
+}
+
+template <int P>
+lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* lin, void* lout, void* scratch, double* gth,
+                           double* gxi) {
+  using R = typename Prec<P>::R;
+  const AdjLayout AL = make_adj_layout(c->p);
+  char* sc = static_cast<char*>(scratch);
+  StepArgs<P> A = make_args_from<P>(c, state);
+  A.rm_out = reinterpret_cast<R*>(sc + AL.rmv);
+  AdjArgs<R> J;
+  J.lin = static_cast<const R*>(lin);
+  J.lout = static_cast<R*>(lout);
+  J.lrn = reinterpret_cast<R*>(sc + AL.lrn);
+  J.lnc = reinterpret_cast<R*>(sc + AL.lnc);
+  J.lglen = reinterpret_cast<R*>(sc + AL.lglen);
+  J.lH = reinterpret_cast<R*>(sc + AL.lH);
+  J.lG = reinterpret_cast<R*>(sc + AL.lG);
+  J.lrr = reinterpret_cast<R*>(sc + AL.lrr);
+  J.lrm = reinterpret_cast<R*>(sc + AL.lrm);
+  J.lgo = reinterpret_cast<R*>(sc + AL.lgo);
+  J.rmv = A.rm_out;
+  J.gtheta = gth;
+  J.partials = reinterpret_cast<double*>(sc + AL.partials);
+  double* sum = reinterpret_cast<double*>(sc + AL.sum);
+  const dim3 gf(c->nb_fluid), ge(c->nb_ext), block(kBlock);
+  // Forward fields of level t.
+  if (c->nb_fluid) hipLaunchKernelGGL(k_colour<P>, gf, block, 0, c->stream, A);
+  if (c->nb_ext) hipLaunchKernelGGL(k_extrap<P>, ge, block, 0, c->stream, A);
+  if (c->nb_fluid) hipLaunchKernelGGL(k_normal<P>, gf, block, 0, c->stream, A);
+  // Reverse pass.
+  HIP_TRY(c, hipMemsetAsync(lout, 0, AL.adj_bytes, c->stream));
+  if (c->nb_fluid) {
+    hipLaunchKernelGGL(k_adj_collide<P>, gf, block, 0, c->stream, A, J);
+    hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kFinish), 0, c->stream, J.partials, c->nb_fluid, sum);
+    hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, c->stream, sum, gxi);
+    hipLaunchKernelGGL(k_adj_normal<P>, gf, block, 0, c->stream, A, J);
+    hipLaunchKernelGGL((k_adj_grad<P, false>), gf, block, 0, c->stream, A, J);
+    if (c->nb_ext) hipLaunchKernelGGL((k_adj_grad<P, true>), ge, block, 0, c->stream, A, J);
+    hipLaunchKernelGGL(k_adj_colour<P>, gf, block, 0, c->stream, A, J);
+    hipLaunchKernelGGL(k_adj_final<P>, gf, block, 0, c->stream, A, J);
+  }
+  HIP_TRY(c, hipGetLastError());
+  return LBM_OK;
+}
+
 #define DISPATCH(ctx, fn, ...)                                   \
   switch ((ctx)->p.precision) {                                  \
     case LBM_FP64: return fn<0>((ctx), __VA_ARGS__);             \
@@ -608,6 +706,16 @@ lbm_status lbm_geometry(lbm_ctx* c, void* d_info, void* d_wet) {
   return LBM_OK;
 }
 
+lbm_status lbm_state_layout(const lbm_params* params, size_t* f_off, size_t* a_off, size_t* g_off) {
+  lbm_status s = check_params(params, g_err, sizeof(g_err));
+  if (s != LBM_OK) return s;
+  const Layout L = make_layout(*params);
+  if (f_off) *f_off = L.f_off;
+  if (a_off) *a_off = L.a_off;
+  if (g_off) *g_off = L.g_off;
+  return LBM_OK;
+}
+
 lbm_status lbm_get_state(lbm_ctx* c, void* d_dst) {
   if (!c) return LBM_ERR_ARG;
   if (!d_dst) return fail(c, LBM_ERR_ARG, "destination is NULL");
@@ -641,6 +749,30 @@ lbm_status lbm_kernel_times(lbm_ctx* c, double* kernel_ms, int64_t* steps) {
   for (int k = 0; k < 4; ++k) kernel_ms[k] = c->kernel_ms[k];
   if (steps) *steps = c->prof_steps;
   return LBM_OK;
+}
+
+lbm_status lbm_adjoint_bytes(const lbm_params* params, size_t* adj_bytes, size_t* scratch_bytes) {
+  lbm_status s = check_params(params, g_err, sizeof(g_err));
+  if (s != LBM_OK) return s;
+  const AdjLayout AL = make_adj_layout(*params);
+  if (adj_bytes) *adj_bytes = AL.adj_bytes;
+  if (scratch_bytes) *scratch_bytes = AL.total;
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_seed(lbm_ctx* c, const void* d_state, void* d_adj) {
+  if (!c) return LBM_ERR_ARG;
+  if (!d_state || !d_adj) return fail(c, LBM_ERR_ARG, "state and adjoint buffers are required");
+  DISPATCH(c, launch_adj_seed, d_state, d_adj);
+}
+
+lbm_status lbm_adjoint_step(lbm_ctx* c, const void* d_state, const void* d_adj_in, void* d_adj_out, void* d_scratch,
+                            double* d_grad_theta, double* d_grad_xi) {
+  if (!c) return LBM_ERR_ARG;
+  if (!d_state || !d_adj_in || !d_adj_out || !d_scratch || !d_grad_theta || !d_grad_xi)
+    return fail(c, LBM_ERR_ARG, "all buffers are required");
+  if (d_adj_in == d_adj_out) return fail(c, LBM_ERR_ARG, "adjoint input and output must differ");
+  DISPATCH(c, launch_adj_step, d_state, d_adj_in, d_adj_out, d_scratch, d_grad_theta, d_grad_xi);
 }
 
 int64_t lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }

@@ -101,6 +101,7 @@ struct StepArgs {
   R* aout;
   S* gout;
   R* rhoN;       // 1 plane
+  R* rm_out;     // optional: rho^m of each fluid node (adjoint recompute)
   R* nst;        // 4 planes: n*_x, n*_y, n*_z, |grad rho^N|
   const R* wet;  // 4 planes: n_s (x, y, z), cos(theta)
   double* partials;
@@ -150,6 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
     rr += a * fm + R(D::w_over_len(i)) * sgn * cv;
   }
   A.rhoN[n] = (rr + rr - rm) / rm;
+  if (A.rm_out) A.rm_out[n] = rm;
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -1,0 +1,177 @@
+"""GPU adjoint (lbm_adjoint_seed / lbm_adjoint_step) and the checkpointed autograd function.
+
+All in FP64 storage. Pins, independent of the adjoint code:
+  * one step: <lambda_t, dS> against central differences of the forward step (FP64 library);
+    theta and xi parts likewise;
+  * many steps: directional derivatives of L = m^p(T) - m^p(0) against the oracle's forward-mode
+    dual numbers (exact derivatives of the FP64 reference step);
+  * checkpoint-and-recompute gives the same gradient bit for bit as keeping every state;
+  * per-node contact-angle derivatives on sampled wetting nodes against central differences
+    (eps = 1e-4 rad) of the FP64 forward run.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def core():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_15781_amd import core as c
+
+    c.lib()
+    return c
+
+
+def _case(n, seed, wavelength=7.0):
+    from paper_2608_15781_amd import inputs
+
+    solid, _ = inputs.grf_mask((n, n, n), wavelength, seed)
+    rng = np.random.default_rng(seed + 1)
+    theta = np.deg2rad(rng.uniform(60, 120, solid.shape))
+    rr0 = (1 - solid).astype(float)
+    return solid, theta, rr0, np.zeros_like(rr0)
+
+
+KW = dict(tau=0.7, sigma=0.02, beta=0.7, accel=[(2e-5, 0, 0), (2e-5, 0, 0)], species=True, x_open=True)
+
+
+def _sim(core, n, solid, theta, rr0, rp0, xi):
+    return core.Lbm((n, n, n), solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, xi=xi, precision="fp64",
+                    tau_species=0.8, **KW)
+
+
+def _flat(sim, buf):
+    import torch
+
+    f, a, g = sim.state_parts(buf)
+    return torch.cat([f, a, g], 0)
+
+
+def _unflat(sim, vec, like):
+    buf = like.clone()
+    f, a, g = sim.state_parts(buf)
+    f.copy_(vec[:19])
+    a.copy_(vec[19:23])
+    g.copy_(vec[23:30])
+    return buf
+
+
+def test_adjoint_one_step_against_finite_differences(core):
+    import torch
+
+    n, xi = 14, 0.05
+    solid, theta, rr0, rp0 = _case(n, 31)
+    sim = _sim(core, n, solid, theta, rr0, rp0, xi)
+    sim.step(12)
+    S = sim.get_state()
+    fluid = torch.tensor((solid.ravel() == 0).astype(np.float64), device="cuda:0")
+    gen = torch.Generator(device="cuda:0").manual_seed(5)
+    lam1 = torch.randn(30, sim.N, dtype=torch.float64, device="cuda:0", generator=gen) * fluid
+    dS = torch.randn(30, sim.N, dtype=torch.float64, device="cuda:0", generator=gen) * fluid
+    dS[:19] *= 1e-2
+    dS[19] *= 1e-2
+    dS[20:23] *= 1e-3
+    dS[23:] *= 1e-2
+    lam0 = sim.new_adjoint()
+    scratch = sim.new_scratch()
+    gth = torch.zeros(sim.N, dtype=torch.float64, device="cuda:0")
+    gxi = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    sim.adjoint_step(S, lam1, lam0, scratch, gth, gxi)
+    torch.cuda.synchronize()
+    x0 = _flat(sim, S).clone()
+
+    def F(buf, model=sim):
+        model.set_state(buf, 12)
+        model.step(1, reductions=False)
+        return float((lam1 * _flat(model, model.get_state())).sum())
+
+    h = 1e-6
+    fd = (F(_unflat(sim, x0 + h * dS, S)) - F(_unflat(sim, x0 - h * dS, S))) / (2 * h)
+    ad = float((lam0 * dS).sum())
+    print("one-step state: adjoint %.12e fd %.12e" % (ad, fd), flush=True)
+    assert abs(ad - fd) < 1e-6 * abs(fd)
+    # contact angle and reaction rate
+    rng = np.random.default_rng(7)
+    dth = rng.normal(size=solid.shape) * (1 - solid)
+    ht = 1e-6
+    Fp = F(S, _sim(core, n, solid, theta + ht * dth, rr0, rp0, xi))
+    Fm = F(S, _sim(core, n, solid, theta - ht * dth, rr0, rp0, xi))
+    fd_th = (Fp - Fm) / (2 * ht)
+    ad_th = float((gth.cpu().numpy() * dth.ravel()).sum())
+    print("one-step theta: adjoint %.12e fd %.12e" % (ad_th, fd_th), flush=True)
+    assert abs(ad_th - fd_th) < 1e-6 * abs(fd_th)
+    hx = 1e-7
+    fd_xi = (F(S, _sim(core, n, solid, theta, rr0, rp0, xi + hx)) -
+             F(S, _sim(core, n, solid, theta, rr0, rp0, xi - hx))) / (2 * hx)
+    print("one-step xi: adjoint %.12e fd %.12e" % (float(gxi[0]), fd_xi), flush=True)
+    assert abs(float(gxi[0]) - fd_xi) < 1e-6 * abs(fd_xi)
+
+
+def test_gradient_matches_oracle_duals_and_checkpointing(core, oracle_mod):
+    import torch
+
+    from paper_2608_15781_amd import autograd as ag
+
+    n, xi, T = 12, 0.05, 30
+    solid, theta, rr0, rp0 = _case(n, 41, wavelength=6.0)
+    rng = np.random.default_rng(3)
+    d1 = rng.normal(size=solid.shape) * (1 - solid)
+    d2 = rng.normal(size=solid.shape) * (1 - solid)
+    L, dL = oracle_mod.grad((n, n, n), solid, theta, xi, T, dtheta=[d1.ravel(), d2.ravel(), np.zeros(n ** 3)],
+                            dxi=[0.0, 0.0, 1.0], rho_r0=rr0, tau_c=0.8, **KW)
+    sim = _sim(core, n, solid, theta, rr0, rp0, xi)
+    Lg, cps, final = ag.forward_states(sim, T, T)
+    gth, gxi, _ = ag.adjoint_gradients(sim, T, T, cps, final)
+    g = gth.cpu().numpy()
+    ad = [float(g @ d1.ravel()), float(g @ d2.ravel()), float(gxi)]
+    print("L gpu %.12e oracle %.12e" % (Lg, L), flush=True)
+    print("dL adjoint", ad, "oracle duals", list(dL), flush=True)
+    assert abs(Lg - L) < 1e-10 * abs(L)
+    for a, b in zip(ad, dL):
+        assert abs(a - b) < 1e-8 * abs(b) + 1e-14, (a, b)
+    # checkpoint-and-recompute (every 7 steps) reproduces the gradient exactly
+    sim2 = _sim(core, n, solid, theta, rr0, rp0, xi)
+    L2, cps2, final2 = ag.forward_states(sim2, T, 7)
+    gth2, gxi2, _ = ag.adjoint_gradients(sim2, T, 7, cps2, final2)
+    assert torch.equal(gth2, gth) and float(gxi2) == float(gxi)
+    # the autograd function
+    th_t = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    xi_t = torch.tensor(xi, dtype=torch.float64, requires_grad=True)
+    problem = dict(shape=(n, n, n), solid=solid, rho_r0=rr0, rho_p0=rp0, precision="fp64", steps=T, checkpoint=7,
+                   params=dict(tau_species=0.8, **KW))
+    Lt = ag.gas_production(th_t, xi_t, problem)
+    Lt.backward()
+    assert abs(float(Lt) - Lg) <= 1e-12 * abs(Lg)
+    assert np.array_equal(th_t.grad.numpy().ravel(), g)
+    assert float(xi_t.grad) == float(gxi)
+
+
+def test_contact_angle_gradient_finite_differences_on_wall_nodes(core):
+    from paper_2608_15781_amd import autograd as ag
+
+    n, xi, T = 18, 0.05, 40
+    solid, theta, rr0, rp0 = _case(n, 51)
+    sim = _sim(core, n, solid, theta, rr0, rp0, xi)
+    L0, cps, final = ag.forward_states(sim, T, 10)
+    gth, gxi, _ = ag.adjoint_gradients(sim, T, 10, cps, final)
+    g = gth.cpu().numpy()
+    order = np.argsort(-np.abs(g))
+    rng = np.random.default_rng(9)
+    wet = np.flatnonzero(g != 0)
+    picks = list(order[:4]) + list(rng.choice(wet, 4, replace=False))
+    eps = 1e-4
+    for k in picks:
+        tp = theta.ravel().copy()
+        tm = theta.ravel().copy()
+        tp[k] += eps
+        tm[k] -= eps
+        Lp = float(_sim(core, n, solid, tp.reshape(solid.shape), rr0, rp0, xi).step(T)[:, 2].sum())
+        Lm = float(_sim(core, n, solid, tm.reshape(solid.shape), rr0, rp0, xi).step(T)[:, 2].sum())
+        fd = (Lp - Lm) / (2 * eps)
+        print("node %d adjoint %.10e fd %.10e" % (k, g[k], fd), flush=True)
+        assert abs(g[k] - fd) < 1e-5 * abs(g[order[0]]) + 1e-6 * abs(fd), (k, g[k], fd)
