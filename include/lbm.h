@@ -130,14 +130,15 @@ lbm_status lbm_populations(lbm_ctx* ctx, void* d_fr, void* d_fp, void* d_g);
 /* Static geometry computed at init, for inspection: d_info (uint32 N) holds, at fluid nodes,
  * bit i (i < 18) = node x - c_i is solid, bit 18 = fluid, bit 19 = wetting node (some
  * neighbour solid), bits 20..22 = r(x) * NN(x); at solid nodes bit i (i < 18) = node x + c_i
- * is fluid and bit 23 = colour is extrapolated into this node. d_wet (4N, real type): unit
- * solid normal n_s (components 0..2, zero where undefined) and cos(theta) (component 3).
+ * is fluid and bit 23 = colour is extrapolated into this node. d_wet (4N, real type, node-major
+ * [4*n + k]): unit solid normal n_s (k = 0..2, zero where undefined) and cos(theta) (k = 3).
  * Either may be NULL. */
 lbm_status lbm_geometry(lbm_ctx* ctx, void* d_info, void* d_wet);
 
 /* Byte offsets inside a state snapshot of its three parts: the 19 colour-blind population
- * planes (storage type, population-major), the 4 colour-scalar planes a, v_x, v_y, v_z (real
- * type) and the 7 species planes (storage type; absent without species). In the *_DEV storages a
+ * planes (storage type, population-major [i*N + n]), the colour scalars as one 4-vector per node
+ * (a, v_x, v_y, v_z; real type, node-major [4*n + k]) and the 7 species planes (storage type;
+ * absent without species). In the *_DEV storages a
  * population f is stored as (f - w_i) * 2^k (k = fp16_scale_log2 for FP16, 0 for BF16). */
 lbm_status lbm_state_layout(const lbm_params* params, size_t* f_off, size_t* a_off, size_t* g_off);
 

@@ -222,7 +222,7 @@ class Lbm:
         wet = t.empty(4 * self.N, dtype=self.real, device=self.device)
         self._check(lib().lbm_geometry(self._h, info.data_ptr(), wet.data_ptr()), self._h)
         self.stream.synchronize()
-        return info, wet.view(4, self.N)
+        return info, wet.view(self.N, 4).t()
 
     def get_state(self):
         buf = self.torch.empty(self.state_bytes, dtype=self.torch.uint8, device=self.device)
@@ -239,7 +239,8 @@ class Lbm:
         return f.value, a.value, g.value
 
     def state_parts(self, buf):
-        """Views (19, N), (4, N), (7, N) of a state snapshot (FP32/FP64 storage only)."""
+        """Views (19, N), (4, N), (7, N) of a state snapshot (FP32/FP64 storage only); the colour
+        scalars are stored node-major, so their (4, N) view is strided."""
         t = self.torch
         if self.precision not in (0, 1):
             raise ValueError("state_parts needs FP32 or FP64 storage")
@@ -248,7 +249,7 @@ class Lbm:
         f_off, a_off, g_off = self.state_layout()
         N = self.N
         f = buf[f_off:f_off + 19 * N * es].view(dt).view(19, N)
-        a = buf[a_off:a_off + 4 * N * es].view(dt).view(4, N)
+        a = buf[a_off:a_off + 4 * N * es].view(dt).view(N, 4).t()
         g = buf[g_off:g_off + 7 * N * es].view(dt).view(7, N) if self.params.species else None
         return f, a, g
 

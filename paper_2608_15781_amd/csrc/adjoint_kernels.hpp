@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(StepArgs<P> A, typename Pre
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
   const size_t N = A.N;
-  const R a = A.ain[n];
+  const R a = ld4(A.ain, n).x;
   R s = 0;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
   const int t = logical_block() * kBlock + threadIdx.x;
   double gxi = 0.0;
   const int n = (t < A.nfluid) ? A.fluid[t] : 0;
-  const uint32_t inf = (t < A.nfluid) ? A.info[n] : 0u;
+  const uint32_t inf = (t < A.nfluid) ? A.finfo[t] : 0u;
   if (inf & kFluid) {
     const Nbr nb = make_nbr(n, A.geo);
     const size_t N = A.N;
@@ -137,8 +137,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     const R rn = A.rhoN[n];
     const R rr = R(0.5) * rm * (R(1) + rn);
     const R rp = R(0.5) * rm * (R(1) - rn);
-    const R nn[3] = {A.nst[n], A.nst[N + n], A.nst[2 * N + n]};
-    const R glen = A.nst[3 * N + n];
+    const typename V4<R>::T nsv = ld4(A.nst, n);
+    const R nn[3] = {nsv.x, nsv.y, nsv.z};
+    const R glen = nsv.w;
     const bool has_n = glen > A.eps;
     R H = 0;
     R Jm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -147,9 +148,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
       for (int i = 0; i < 18; ++i) {
         const bool sol = (inf >> D::opp[i]) & 1u;
         const int m = nb.at(D::cx[i], D::cy[i], D::cz[i]);
-        const R a0 = sol ? nn[0] : A.nst[m];
-        const R a1 = sol ? nn[1] : A.nst[N + m];
-        const R a2 = sol ? nn[2] : A.nst[2 * N + m];
+        const typename V4<R>::T mv = sol ? nsv : ld4(A.nst, m);
+        const R a0 = mv.x, a1 = mv.y, a2 = mv.z;
         const R w3 = R(3.0 * D::w(i));
         if (D::cx[i]) { Jm[0][0] += w3 * R(D::cx[i]) * a0; Jm[1][0] += w3 * R(D::cx[i]) * a1; Jm[2][0] += w3 * R(D::cx[i]) * a2; }
         if (D::cy[i]) { Jm[0][1] += w3 * R(D::cy[i]) * a0; Jm[1][1] += w3 * R(D::cy[i]) * a1; Jm[2][1] += w3 * R(D::cy[i]) * a2; }
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
   const int t = logical_block() * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
-  const uint32_t inf = A.info[n];
+  const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
   R mu[3] = {J.lnc[n], J.lnc[N + n], J.lnc[2 * N + n]};
@@ -448,7 +448,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
     const int m = nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
     const R lh = J.lH[m];
     if (lh == R(0)) continue;
-    const R q0 = A.nst[m], q1 = A.nst[N + m], q2 = A.nst[2 * N + m];
+    const typename V4<R>::T qv = ld4(A.nst, m);
+    const R q0 = qv.x, q1 = qv.y, q2 = qv.z;
     const R cn = R(D::cx[i]) * q0 + R(D::cy[i]) * q1 + R(D::cz[i]) * q2;
     const R w3 = R(-3.0 * D::w(i)) * lh;
     mu[0] += w3 * (R(D::cx[i]) - q0 * cn);
@@ -473,9 +474,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
     const R nv[3] = {g[0] * il, g[1] * il, g[2] * il};
     R ln[3] = {mu[0], mu[1], mu[2]};
     if (inf & kWet) {
-      const R sx = A.wet[n], sy = A.wet[N + n], sz = A.wet[2 * N + n];
+      const typename V4<R>::T wv = ld4(A.wet, n);
+      const R sx = wv.x, sy = wv.y, sz = wv.z;
       if (sx * sx + sy * sy + sz * sz > R(0.5)) {
-        const R ct = A.wet[3 * N + n];
+        const R ct = wv.w;
         const R st = sqrt(fmax(R(0), (R(1) - ct) * (R(1) + ct)));
         const R cp = sx * nv[0] + sy * nv[1] + sz * nv[2];
         const R c0 = nv[1] * sz - nv[2] * sy, c1 = nv[2] * sx - nv[0] * sz, c2 = nv[0] * sy - nv[1] * sx;
@@ -516,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(StepArgs<P> A, AdjArgs<type
   const int t = logical_block() * kBlock + threadIdx.x;
   if (t >= (EXT ? A.next : A.nfluid)) return;
   const int n = EXT ? A.ext[t] : A.fluid[t];
-  const uint32_t inf = A.info[n];
+  const uint32_t inf = EXT ? A.einfo[t] : A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
   R s = 0;
@@ -546,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_colour(StepArgs<P> A, AdjArgs<ty
   const int t = logical_block() * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
-  const uint32_t inf = A.info[n];
+  const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   R l = J.lrn[n];
 #pragma unroll
@@ -578,10 +580,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_final(StepArgs<P> A, AdjArgs<typ
   const int t = logical_block() * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
-  const uint32_t inf = A.info[n];
+  const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
-  const R a = A.ain[n];
+  const R a = ld4(A.ain, n).x;
   R la = 0, lv[3] = {0, 0, 0};
 #pragma unroll
   for (int q = 0; q < 19; ++q) {

@@ -29,7 +29,7 @@ size_t store_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precisio
 size_t real_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 
 struct Layout {
-  size_t info, wet, rhoN, nst, state[2], partials, ring, lists[2], counts, total;
+  size_t info, wet, rhoN, nst, state[2], partials, ring, lists[2], linfo[2], counts, total;
   size_t f_off, a_off, g_off, state_bytes;  // within one state buffer
   int nblocks;  // one thread per node, rounded up to a multiple of kXcd workgroups
 };
@@ -56,6 +56,8 @@ Layout make_layout(const lbm_params& p) {
   L.ring = o; o = align_up(o + 5 * sizeof(double) * kRing);
   L.lists[0] = o; o = align_up(o + 4 * N);  // fluid nodes
   L.lists[1] = o; o = align_up(o + 4 * N);  // solid nodes with extrapolated colour
+  L.linfo[0] = o; o = align_up(o + 4 * N);  // info words of the list entries
+  L.linfo[1] = o; o = align_up(o + 4 * N);
   L.counts = o; o = align_up(o + 4 * (size_t(nb) + 2));
   L.total = o;
   return L;
@@ -221,10 +223,7 @@ __global__ void k_init_wet(int nx, int ny, int nz, const uint8_t* solid, const u
   }
   double len = sqrt(double(sx * sx + sy * sy + sz * sz));
   double il = len > 0 ? 1.0 / len : 0.0;
-  wet[n] = R(sx * il);
-  wet[N + n] = R(sy * il);
-  wet[2 * N + n] = R(sz * il);
-  wet[3 * N + n] = R(cos(th));
+  st4(wet, n, R(sx * il), R(sy * il), R(sz * il), R(cos(th)));
 }
 
 // S_0 = f^eq(rho^k_0, 0) per colour: f^m = w (rho^r + rho^p), a = rho^r / rho^m, v = 0, g = w C_0.
@@ -238,10 +237,7 @@ __global__ void k_init_state(StepArgs<P> A, const double* rr0, const double* rp0
   const bool fluid = A.info[n] & kFluid;
   const double rm = fluid ? rr0[n] + rp0[n] : 1.0;
   for (int i = 0; i < 19; ++i) A.fout[size_t(i) * N + n] = Prec<P>::st(R(D::w(i) * rm), R(D::w(i)), A.scale);
-  A.aout[n] = fluid ? R(rr0[n] / rm) : R(0);
-  A.aout[N + n] = 0;
-  A.aout[2 * N + n] = 0;
-  A.aout[3 * N + n] = 0;
+  st4(A.aout, n, fluid ? R(rr0[n] / rm) : R(0), R(0), R(0), R(0));
   if (A.species) {
     const double c = c0 ? c0[n] : 1.0;
     for (int i = 0; i < 7; ++i) A.gout[size_t(i) * N + n] = Prec<P>::st(R(D3Q7::w(i) * c), R(D3Q7::w(i)), A.gscale);
@@ -254,6 +250,11 @@ __global__ void k_flag_count(const uint32_t* info, int N, uint32_t mask, int* co
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = __syncthreads_count(n < N && (info[n] & mask));
   if (threadIdx.x == 0) counts[blockIdx.x] = c;
+}
+
+__global__ void k_gather_info(const uint32_t* info, const int* list, int len, uint32_t* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < len) out[t] = info[list[t]];
 }
 
 __global__ void k_scan_counts(int* counts, int nb) {
@@ -321,8 +322,10 @@ StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
   A.geo.fx = make_fastdiv(uint32_t(p.nx));
   A.geo.fy = make_fastdiv(uint32_t(p.ny));
   A.fluid = reinterpret_cast<const int*>(c->ws + L.lists[0]);
+  A.finfo = reinterpret_cast<const uint32_t*>(c->ws + L.linfo[0]);
   A.nfluid = c->nfluid;
   A.ext = reinterpret_cast<const int*>(c->ws + L.lists[1]);
+  A.einfo = reinterpret_cast<const uint32_t*>(c->ws + L.linfo[1]);
   A.next = c->next;
   A.info = reinterpret_cast<const uint32_t*>(c->ws + L.info);
   char* sb = c->ws + L.state[src_buf];
@@ -431,6 +434,11 @@ lbm_status launch_init(lbm_ctx* c, const uint8_t* d_solid, const uint8_t* d_reac
   }
   c->nfluid = lens[0];
   c->next = lens[1];
+  for (int k = 0; k < 2; ++k)
+    if (lens[k] > 0)
+      hipLaunchKernelGGL(k_gather_info, dim3((lens[k] + tb - 1) / tb), dim3(tb), 0, c->stream, info,
+                         reinterpret_cast<const int*>(c->ws + c->L.lists[k]), lens[k],
+                         reinterpret_cast<uint32_t*>(c->ws + c->L.linfo[k]));
   c->nb_fluid = rounded_blocks(c->nfluid);
   c->nb_ext = rounded_blocks(c->next);
   // The initial state goes into buffer 0 (make_args with src 1 writes buffer 0).

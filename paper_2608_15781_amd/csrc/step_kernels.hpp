@@ -32,7 +32,21 @@
 namespace lbm {
 
 constexpr int kBlock = 256;
-constexpr int kXcd = 8;  // MI355X: 8 XCDs; workgroups are dealt round-robin across them
+constexpr int kXcd = 8;
+
+// Per-node 4-vectors (colour scalars a, v; realigned normal and |G|; wetting data) are stored
+// together (16 or 32 bytes per node) so that one load brings all four.
+template <class R> struct V4;
+template <> struct V4<float> { using T = float4; };
+template <> struct V4<double> { using T = double4; };
+template <class R>
+__device__ inline typename V4<R>::T ld4(const R* p, size_t n) { return reinterpret_cast<const typename V4<R>::T*>(p)[n]; }
+template <class R>
+__device__ inline void st4(R* p, size_t n, R x, R y, R z, R w) {
+  typename V4<R>::T v;
+  v.x = x; v.y = y; v.z = z; v.w = w;
+  reinterpret_cast<typename V4<R>::T*>(p)[n] = v;
+}  // MI355X: 8 XCDs; workgroups are dealt round-robin across them
 
 // Maps the hardware workgroup id to a logical tile so that each XCD (with its own L2) works on
 // one contiguous slab of the lattice; neighbouring rows then share that XCD's L2.
@@ -88,22 +102,24 @@ struct StepArgs {
   using R = typename Prec<P>::R;
   int nx, ny, nz, N;
   Geom geo;
-  const int* fluid;  // dense indices of the fluid nodes, in increasing order
+  const int* fluid;       // dense indices of the fluid nodes, in increasing order
+  const uint32_t* finfo;  // their info words
   int nfluid;
-  const int* ext;    // dense indices of the solid nodes whose colour is extrapolated
+  const int* ext;         // dense indices of the solid nodes whose colour is extrapolated
+  const uint32_t* einfo;  // their info words
   int next;
   const uint32_t* info;
   // state in (pull source) and out
   const S* fin;  // 19 planes f^m
-  const R* ain;  // 4 planes a, vx, vy, vz
+  const R* ain;  // per node 4-vector (a, vx, vy, vz)
   const S* gin;  // 7 planes species
   S* fout;
   R* aout;
   S* gout;
   R* rhoN;       // 1 plane
   R* rm_out;     // optional: rho^m of each fluid node (adjoint recompute)
-  R* nst;        // 4 planes: n*_x, n*_y, n*_z, |grad rho^N|
-  const R* wet;  // 4 planes: n_s (x, y, z), cos(theta)
+  R* nst;        // per node 4-vector (n*_x, n*_y, n*_z, |grad rho^N|)
+  const R* wet;  // per node 4-vector (n_s, cos(theta))
   double* partials;
   double* ring_row;  // 5 doubles of this step
   R relax;           // 1 - 1/tau
@@ -131,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
   const int t = logical_block() * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
-  const uint32_t inf = A.info[n];
+  const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
   R rm = 0, rr = 0;
@@ -142,11 +158,12 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
     const int q = bb ? D::opp[i] : i;
     const R sgn = bb ? R(-1) : R(1);  // c_q = sgn * c_i
     const R fm = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
-    const R a = A.ain[src];
+    const typename V4<R>::T av = ld4(A.ain, src);
     R cv = 0;
-    if (D::cx[i]) cv += R(D::cx[i]) * A.ain[N + src];
-    if (D::cy[i]) cv += R(D::cy[i]) * A.ain[2 * N + src];
-    if (D::cz[i]) cv += R(D::cz[i]) * A.ain[3 * N + src];
+    if (D::cx[i]) cv += R(D::cx[i]) * av.y;
+    if (D::cy[i]) cv += R(D::cy[i]) * av.z;
+    if (D::cz[i]) cv += R(D::cz[i]) * av.w;
+    const R a = av.x;
     rm += fm;
     rr += a * fm + R(D::w_over_len(i)) * sgn * cv;
   }
@@ -164,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs<P> A) {
   const int t = logical_block() * kBlock + threadIdx.x;
   if (t >= A.next) return;
   const int n = A.ext[t];
-  const uint32_t inf = A.info[n];
+  const uint32_t inf = A.einfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   R num = 0, den = 0;
 #pragma unroll
@@ -190,9 +207,8 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
   const int t = logical_block() * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
-  const uint32_t inf = A.info[n];
+  const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
-  const size_t N = A.N;
   R g[3] = {0, 0, 0};
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
@@ -209,9 +225,10 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
     const R il = R(1) / len;
     nv[0] = g[0] * il; nv[1] = g[1] * il; nv[2] = g[2] * il;
     if (inf & kWet) {
-      const R sx = A.wet[n], sy = A.wet[N + n], sz = A.wet[2 * N + n];
+      const typename V4<R>::T wv = ld4(A.wet, n);
+      const R sx = wv.x, sy = wv.y, sz = wv.z;
       if (sx * sx + sy * sy + sz * sz > R(0.5)) {
-        const R ct = A.wet[3 * N + n];
+        const R ct = wv.w;
         const R st = sqrt(fmax(R(0), (R(1) - ct) * (R(1) + ct)));
         // cos and sin of theta' from the dot and cross products (accurate next to +-n_s).
         const R cp = sx * nv[0] + sy * nv[1] + sz * nv[2];
@@ -231,10 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
       }
     }
   }
-  A.nst[n] = nv[0];
-  A.nst[N + n] = nv[1];
-  A.nst[2 * N + n] = nv[2];
-  A.nst[3 * N + n] = len;
+  st4(A.nst, n, nv[0], nv[1], nv[2], len);
 }
 
 // T^{-1} k* of Appendix A (eq. back_transformation_vector), regrouped with common
@@ -354,11 +368,12 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
   const int t = logical_block() * kBlock + threadIdx.x;
   double red5[5] = {0, 0, 0, 0, 0};
   const int n = (t < A.nfluid) ? A.fluid[t] : 0;
-  const uint32_t inf = (t < A.nfluid) ? A.info[n] : 0u;
+  const uint32_t inf = (t < A.nfluid) ? A.finfo[t] : 0u;
   if (inf & kFluid) {
     const Nbr nb = make_nbr(n, A.geo);
     const size_t N = A.N;
-    // Pull streaming with halfway bounce-back: f^m_i(x) = S^m_i(x - c_i), or S^m_opp(i)(x).
+    // All loads of the node first (pull of f^m and g with halfway bounce-back, rho^N, the node's
+    // and its neighbours' realigned normals), so that one memory round trip covers them.
     R f[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
@@ -366,6 +381,27 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
       const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
       const int q = bb ? D::opp[i] : i;
       f[i] = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
+    }
+    R g[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (A.species) {
+      const bool outlet = inf & kOutlet;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const bool own = (i == 1 && outlet);  // zero-gradient outflow: the node's own S_1
+        const bool bb = !own && ((inf >> i) & 1u);
+        const int src = (own || bb) ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+        const int q = own ? 1 : (bb ? D3Q7::opp[i] : i);
+        g[i] = Prec<P>::ld(A.gin[size_t(q) * N + src], R(D3Q7::w(i)), A.inv_gscale);
+      }
+      g[6] = Prec<P>::ld(A.gin[6 * N + n], R(D3Q7::w(6)), A.inv_gscale);
+    }
+    const R rn = A.rhoN[n];
+    const typename V4<R>::T nsv = ld4(A.nst, n);
+    typename V4<R>::T nbv[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) {
+      const bool sol = (inf >> D::opp[i]) & 1u;  // x + c_i is solid: its normal is not stored
+      nbv[i] = sol ? nsv : ld4(A.nst, nb.at(D::cx[i], D::cy[i], D::cz[i]));
     }
     // Moments (same summation order as k_colour, so rho^m agrees bit for bit).
     R rm = 0;
@@ -383,30 +419,25 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
     }
     const R irm = R(1) / rm;
     const R ux = mx * irm, uy = my * irm, uz = mz * irm;
-    const R rn = A.rhoN[n];
     const R rr = R(0.5) * rm * (R(1) + rn);
     const R rp = R(0.5) * rm * (R(1) - rn);
 
     // Realigned unit normal and gradient magnitude; curvature H = -(tr J - n.J.n) with
     // J_ab = 3 sum_i w_i c_ib n*_a(x + c_i), a solid neighbour contributing n*(x).
-    const R n0 = A.nst[n], n1 = A.nst[N + n], n2 = A.nst[2 * N + n];
-    const R glen = A.nst[3 * N + n];
+    const R n0 = nsv.x, n1 = nsv.y, n2 = nsv.z;
+    const R glen = nsv.w;
     const bool has_n = glen > A.eps;
+    R J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int i = 0; i < 18; ++i) {
+      const R a0 = nbv[i].x, a1 = nbv[i].y, a2 = nbv[i].z;
+      const R w3 = R(3.0 * D::w(i));
+      if (D::cx[i]) { J[0][0] += w3 * R(D::cx[i]) * a0; J[1][0] += w3 * R(D::cx[i]) * a1; J[2][0] += w3 * R(D::cx[i]) * a2; }
+      if (D::cy[i]) { J[0][1] += w3 * R(D::cy[i]) * a0; J[1][1] += w3 * R(D::cy[i]) * a1; J[2][1] += w3 * R(D::cy[i]) * a2; }
+      if (D::cz[i]) { J[0][2] += w3 * R(D::cz[i]) * a0; J[1][2] += w3 * R(D::cz[i]) * a1; J[2][2] += w3 * R(D::cz[i]) * a2; }
+    }
     R H = 0;
     if (has_n) {
-      R J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-      for (int i = 0; i < 18; ++i) {
-        const bool sol = (inf >> D::opp[i]) & 1u;
-        const int m = nb.at(D::cx[i], D::cy[i], D::cz[i]);
-        const R a0 = sol ? n0 : A.nst[m];
-        const R a1 = sol ? n1 : A.nst[N + m];
-        const R a2 = sol ? n2 : A.nst[2 * N + m];
-        const R w3 = R(3.0 * D::w(i));
-        if (D::cx[i]) { J[0][0] += w3 * R(D::cx[i]) * a0; J[1][0] += w3 * R(D::cx[i]) * a1; J[2][0] += w3 * R(D::cx[i]) * a2; }
-        if (D::cy[i]) { J[0][1] += w3 * R(D::cy[i]) * a0; J[1][1] += w3 * R(D::cy[i]) * a1; J[2][1] += w3 * R(D::cy[i]) * a2; }
-        if (D::cz[i]) { J[0][2] += w3 * R(D::cz[i]) * a0; J[1][2] += w3 * R(D::cz[i]) * a1; J[2][2] += w3 * R(D::cz[i]) * a2; }
-      }
       const R nn[3] = {n0, n1, n2};
       R nJn = 0;
 #pragma unroll
@@ -424,23 +455,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
     const R upy = uy + R(0.5) * (rr * dur[1] + rp * dup[1]) * irm;
     const R upz = uz + R(0.5) * (rr * dur[2] + rp * dup[2]) * irm;
 
-    // Species pull (face directions coincide with D3Q19 directions 0..5).
-    R g[7] = {0, 0, 0, 0, 0, 0, 0};
     R C = R(1);
     if (A.species) {
-      const bool outlet = inf & kOutlet;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        if (i == 1 && outlet) {
-          g[i] = Prec<P>::ld(A.gin[N + n], R(D3Q7::w(1)), A.inv_gscale);
-        } else {
-          const bool bb = (inf >> i) & 1u;
-          const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
-          const int q = bb ? D3Q7::opp[i] : i;
-          g[i] = Prec<P>::ld(A.gin[size_t(q) * N + src], R(D3Q7::w(i)), A.inv_gscale);
-        }
-      }
-      g[6] = Prec<P>::ld(A.gin[6 * N + n], R(D3Q7::w(6)), A.inv_gscale);
       C = 0;
 #pragma unroll
       for (int i = 0; i < 7; ++i) C += g[i];
@@ -508,10 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
       const R v0 = has_n ? vc * n0 : R(0), v1 = has_n ? vc * n1 : R(0), v2 = has_n ? vc * n2 : R(0);
 #pragma unroll
       for (int i = 0; i < 19; ++i) A.fout[size_t(i) * N + n] = Prec<P>::st(fs[i], R(D::w(i)), A.scale);
-      A.aout[n] = aout;
-      A.aout[N + n] = v0;
-      A.aout[2 * N + n] = v1;
-      A.aout[3 * N + n] = v2;
+      st4(A.aout, n, aout, v0, v1, v2);
       bool ok = finite(fsum) && finite(aout) && finite(v0 + v1 + v2) && finite(rr) && finite(rp);
       if (A.species) {
         // BGK towards g^eq = w C (1 + 4 c.u_phys); at the inlet the populations are replaced by
@@ -552,8 +565,10 @@ __global__ __launch_bounds__(kBlock) void k_expand(StepArgs<P> A, typename Prec<
   if (n >= A.N) return;
   const size_t N = A.N;
   const bool fluid = A.info[n] & kFluid;
-  const R a = fluid ? A.ain[n] : R(0);
-  const R v0 = fluid ? A.ain[N + n] : R(0), v1 = fluid ? A.ain[2 * N + n] : R(0), v2 = fluid ? A.ain[3 * N + n] : R(0);
+  typename V4<R>::T av;
+  av.x = av.y = av.z = av.w = R(0);
+  if (fluid) av = ld4(A.ain, n);
+  const R a = av.x, v0 = av.y, v1 = av.z, v2 = av.w;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     R fm = fluid ? Prec<P>::ld(A.fin[size_t(i) * N + n], R(D::w(i)), A.inv_scale) : R(0);

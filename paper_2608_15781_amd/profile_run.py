@@ -41,6 +41,9 @@ def run(args):
     n = args.copy_mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
+    # evict the source from the 256 MB last-level cache before the calibration copy
+    flush = torch.ones(2 * n, dtype=torch.float32, device="cuda:0")
+    del flush
     dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps(dict(workload=args.workload, precision=args.precision, steps=args.steps,
