@@ -153,6 +153,7 @@ class Lbm:
         rr, rp = _host(rho_r0, np.float64, N), _host(rho_p0, np.float64, N)
         c0a = _host(c0, np.float64, N)
         self.solid = solid
+        self.nfluid = int((solid == 0).sum())  # state entries, fluid nodes in node order
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = L.lbm_init(ctypes.byref(self.params), _p(solid), _p(th), float(theta_uniform), _p(react), _p(rr),
@@ -239,8 +240,9 @@ class Lbm:
         return f.value, a.value, g.value
 
     def state_parts(self, buf):
-        """Views (19, N), (4, N), (7, N) of a state snapshot (FP32/FP64 storage only); the colour
-        scalars are stored node-major, so their (4, N) view is strided."""
+        """Views (19, F), (4, F), (7, F) of a state snapshot (FP32/FP64 storage only), F = number of
+        fluid nodes, columns in node order; the colour scalars are stored node-major, so their view
+        is strided."""
         t = self.torch
         if self.precision not in (0, 1):
             raise ValueError("state_parts needs FP32 or FP64 storage")
@@ -248,9 +250,10 @@ class Lbm:
         es = 8 if self.precision == 0 else 4
         f_off, a_off, g_off = self.state_layout()
         N = self.N
-        f = buf[f_off:f_off + 19 * N * es].view(dt).view(19, N)
-        a = buf[a_off:a_off + 4 * N * es].view(dt).view(N, 4).t()
-        g = buf[g_off:g_off + 7 * N * es].view(dt).view(7, N) if self.params.species else None
+        F = self.nfluid
+        f = buf[f_off:f_off + 19 * N * es].view(dt).view(19, N)[:, :F]
+        a = buf[a_off:a_off + 4 * N * es].view(dt).view(N, 4)[:F].t()
+        g = buf[g_off:g_off + 7 * N * es].view(dt).view(7, N)[:, :F] if self.params.species else None
         return f, a, g
 
     def adjoint_bytes(self):
@@ -259,7 +262,8 @@ class Lbm:
         return ab.value, sb.value
 
     def new_adjoint(self):
-        """A zeroed adjoint state: (30, N) tensor of the context's real type."""
+        """A zeroed adjoint state: (30, N) tensor of the context's real type; column f < nfluid is the
+        fluid node of rank f."""
         return self.torch.zeros(30, self.N, dtype=self.real, device=self.device)
 
     def new_scratch(self):

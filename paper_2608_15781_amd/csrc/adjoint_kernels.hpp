@@ -21,8 +21,8 @@
 
 namespace lbm {
 
-// Adjoint-state layout: 30 planes of N reals, same order as the state (19 f^m, a, v_x, v_y,
-// v_z, 7 species).
+// Adjoint-state layout: 30 planes of N reals indexed by fluid id like the state (19 f^m, a,
+// v_x, v_y, v_z, 7 species).
 constexpr int kAdjPlanes = 30;
 constexpr int kAdjA = 19, kAdjV = 20, kAdjG = 23;
 
@@ -84,16 +84,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(StepArgs<P> A, typename Pre
   using D = D3Q19;
   const int t = logical_block() * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
-  const int n = A.fluid[t];
   const size_t N = A.N;
-  const R a = ld4(A.ain, n).x;
+  const R a = ld4(A.ain, t).x;
   R s = 0;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    s += Prec<P>::ld(A.fin[size_t(i) * N + n], R(D::w(i)), A.inv_scale);
-    lout[size_t(i) * N + n] = R(1) - a;
+    s += Prec<P>::ld(A.fin[size_t(i) * N + t], R(D::w(i)), A.inv_scale);
+    lout[size_t(i) * N + t] = R(1) - a;
   }
-  lout[size_t(kAdjA) * N + n] = -s;
+  lout[size_t(kAdjA) * N + t] = -s;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -111,11 +110,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     const Nbr nb = make_nbr(n, A.geo);
     const size_t N = A.N;
     // ---------------- forward recompute ----------------
+    int sid[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) sid[i] = ((inf >> i) & 1u) ? t : A.fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
     R f[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
       const bool bb = (i < 18) && ((inf >> i) & 1u);
-      const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+      const int src = (i < 18) ? sid[i] : t;
       const int q = bb ? D::opp[i] : i;
       f[i] = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
     }
@@ -176,15 +178,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
         if (i == 1 && outlet) {
-          g[i] = Prec<P>::ld(A.gin[N + n], R(D3Q7::w(1)), A.inv_gscale);
+          g[i] = Prec<P>::ld(A.gin[N + t], R(D3Q7::w(1)), A.inv_gscale);
         } else {
           const bool bb = (inf >> i) & 1u;
-          const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
           const int q = bb ? D3Q7::opp[i] : i;
-          g[i] = Prec<P>::ld(A.gin[size_t(q) * N + src], R(D3Q7::w(i)), A.inv_gscale);
+          g[i] = Prec<P>::ld(A.gin[size_t(q) * N + sid[i]], R(D3Q7::w(i)), A.inv_gscale);
         }
       }
-      g[6] = Prec<P>::ld(A.gin[6 * N + n], R(D3Q7::w(6)), A.inv_gscale);
+      g[6] = Prec<P>::ld(A.gin[6 * N + t], R(D3Q7::w(6)), A.inv_gscale);
       C = 0;
 #pragma unroll
       for (int i = 0; i < 7; ++i) C += g[i];
@@ -216,9 +217,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     // ---------------- reverse ----------------
     R lf[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) lf[i] = J.lin[size_t(i) * N + n];
-    const R la = J.lin[size_t(kAdjA) * N + n];
-    const R lv[3] = {J.lin[size_t(kAdjV) * N + n], J.lin[size_t(kAdjV + 1) * N + n], J.lin[size_t(kAdjV + 2) * N + n]};
+    for (int i = 0; i < 19; ++i) lf[i] = J.lin[size_t(i) * N + t];
+    const R la = J.lin[size_t(kAdjA) * N + t];
+    const R lv[3] = {J.lin[size_t(kAdjV) * N + t], J.lin[size_t(kAdjV + 1) * N + t], J.lin[size_t(kAdjV + 2) * N + t]};
     R l_C = 0, l_delta = 0, l_up[3] = {0, 0, 0};
     R l_g[7] = {0, 0, 0, 0, 0, 0, 0};
     if (A.species) {
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
         const R geq = wc * C * (R(1) + R(4) * cu);
         const R gi = inlet ? geq : g[i];
         const R pre = gi + (geq - gi) * A.inv_tau_c;
-        const R lgo = J.lin[size_t(kAdjG + i) * N + n];
+        const R lgo = J.lin[size_t(kAdjG + i) * N + t];
         const R l_pre = lgo * sink;
         l_sink += lgo * pre;
         R l_geq = l_pre * A.inv_tau_c;
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
       if (cy && cz) v += R(cy * cz) * l_pyz;
       // transpose of the pull: the population S_q(src) read by this node as direction i
       const bool bb = (i < 18) && ((inf >> i) & 1u);
-      const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+      const int src = (i < 18) ? sid[i] : t;
       const int q = bb ? D::opp[i] : i;
       J.lout[size_t(q) * N + src] = v;
     }
@@ -408,12 +409,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
           J.lgo[n] = l_g[1];
         } else {
           const bool bb = (inf >> i) & 1u;
-          const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
           const int q = bb ? D3Q7::opp[i] : i;
-          J.lout[size_t(kAdjG + q) * N + src] = l_g[i];
+          J.lout[size_t(kAdjG + q) * N + sid[i]] = l_g[i];
         }
       }
-      J.lout[size_t(kAdjG + 6) * N + n] = l_g[6];
+      J.lout[size_t(kAdjG + 6) * N + t] = l_g[6];
     }
     J.lrn[n] = l_rn;
     J.lnc[n] = l_n[0];
@@ -583,26 +583,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_final(StepArgs<P> A, AdjArgs<typ
   const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
-  const R a = ld4(A.ain, n).x;
+  const R a = ld4(A.ain, t).x;
   R la = 0, lv[3] = {0, 0, 0};
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
     const bool self = (q == 18) || ((inf >> D::opp[q]) & 1u);  // y + c_q solid: bounce-back reader
     const int rd = self ? n : nb.at(D::cx[q], D::cy[q], D::cz[q]);
     const R lr = J.lrr[rd], lm = J.lrm[rd];
-    const R fq = Prec<P>::ld(A.fin[size_t(q) * N + n], R(D::w(q)), A.inv_scale);
-    J.lout[size_t(q) * N + n] += lr * a + lm;
+    const R fq = Prec<P>::ld(A.fin[size_t(q) * N + t], R(D::w(q)), A.inv_scale);
+    J.lout[size_t(q) * N + t] += lr * a + lm;
     la += lr * fq;
     const R wl = R(D::w_over_len(q)) * lr;
     lv[0] += wl * R(D::cx[q]);
     lv[1] += wl * R(D::cy[q]);
     lv[2] += wl * R(D::cz[q]);
   }
-  J.lout[size_t(kAdjA) * N + n] = la;
-  J.lout[size_t(kAdjV) * N + n] = lv[0];
-  J.lout[size_t(kAdjV + 1) * N + n] = lv[1];
-  J.lout[size_t(kAdjV + 2) * N + n] = lv[2];
-  if (A.species && (inf & kOutlet)) J.lout[size_t(kAdjG + 1) * N + n] += J.lgo[n];
+  J.lout[size_t(kAdjA) * N + t] = la;
+  J.lout[size_t(kAdjV) * N + t] = lv[0];
+  J.lout[size_t(kAdjV + 1) * N + t] = lv[1];
+  J.lout[size_t(kAdjV + 2) * N + t] = lv[2];
+  if (A.species && (inf & kOutlet)) J.lout[size_t(kAdjG + 1) * N + t] += J.lgo[n];
 }
 
 __global__ void k_add_scalar(const double* src, double* dst) {

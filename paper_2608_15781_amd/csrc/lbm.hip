@@ -29,7 +29,7 @@ size_t store_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precisio
 size_t real_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 
 struct Layout {
-  size_t info, wet, rhoN, nst, state[2], partials, ring, lists[2], linfo[2], counts, total;
+  size_t info, wet, rhoN, nst, state[2], partials, ring, lists[2], linfo[2], fid, counts, total;
   size_t f_off, a_off, g_off, state_bytes;  // within one state buffer
   int nblocks;  // one thread per node, rounded up to a multiple of kXcd workgroups
 };
@@ -58,6 +58,7 @@ Layout make_layout(const lbm_params& p) {
   L.lists[1] = o; o = align_up(o + 4 * N);  // solid nodes with extrapolated colour
   L.linfo[0] = o; o = align_up(o + 4 * N);  // info words of the list entries
   L.linfo[1] = o; o = align_up(o + 4 * N);
+  L.fid = o; o = align_up(o + 4 * N);       // node -> fluid id
   L.counts = o; o = align_up(o + 4 * (size_t(nb) + 2));
   L.total = o;
   return L;
@@ -231,16 +232,16 @@ template <int P>
 __global__ void k_init_state(StepArgs<P> A, const double* rr0, const double* rp0, const double* c0) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= A.N) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= A.nfluid) return;
+  const int n = A.fluid[t];
   const size_t N = A.N;
-  const bool fluid = A.info[n] & kFluid;
-  const double rm = fluid ? rr0[n] + rp0[n] : 1.0;
-  for (int i = 0; i < 19; ++i) A.fout[size_t(i) * N + n] = Prec<P>::st(R(D::w(i) * rm), R(D::w(i)), A.scale);
-  st4(A.aout, n, fluid ? R(rr0[n] / rm) : R(0), R(0), R(0), R(0));
+  const double rm = rr0[n] + rp0[n];
+  for (int i = 0; i < 19; ++i) A.fout[size_t(i) * N + t] = Prec<P>::st(R(D::w(i) * rm), R(D::w(i)), A.scale);
+  st4(A.aout, t, R(rr0[n] / rm), R(0), R(0), R(0));
   if (A.species) {
     const double c = c0 ? c0[n] : 1.0;
-    for (int i = 0; i < 7; ++i) A.gout[size_t(i) * N + n] = Prec<P>::st(R(D3Q7::w(i) * c), R(D3Q7::w(i)), A.gscale);
+    for (int i = 0; i < 7; ++i) A.gout[size_t(i) * N + t] = Prec<P>::st(R(D3Q7::w(i) * c), R(D3Q7::w(i)), A.gscale);
   }
 }
 
@@ -255,6 +256,13 @@ __global__ void k_flag_count(const uint32_t* info, int N, uint32_t mask, int* co
 __global__ void k_gather_info(const uint32_t* info, const int* list, int len, uint32_t* out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < len) out[t] = info[list[t]];
+}
+
+// Fluid id of every node (-1 for solid): the inverse of the fluid list.
+__global__ void k_fill_fid(const uint32_t* info, const int* list, int N, int nfluid, int* fid) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < N && !(info[n] & kFluid)) fid[n] = -1;
+  if (n < nfluid) fid[list[n]] = n;
 }
 
 __global__ void k_scan_counts(int* counts, int nb) {
@@ -326,6 +334,7 @@ StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
   A.nfluid = c->nfluid;
   A.ext = reinterpret_cast<const int*>(c->ws + L.lists[1]);
   A.einfo = reinterpret_cast<const uint32_t*>(c->ws + L.linfo[1]);
+  A.fid = reinterpret_cast<const int*>(c->ws + L.fid);
   A.next = c->next;
   A.info = reinterpret_cast<const uint32_t*>(c->ws + L.info);
   char* sb = c->ws + L.state[src_buf];
@@ -434,6 +443,9 @@ lbm_status launch_init(lbm_ctx* c, const uint8_t* d_solid, const uint8_t* d_reac
   }
   c->nfluid = lens[0];
   c->next = lens[1];
+  hipLaunchKernelGGL(k_fill_fid, dim3(gb), dim3(tb), 0, c->stream, info,
+                     reinterpret_cast<const int*>(c->ws + c->L.lists[0]), c->N, c->nfluid,
+                     reinterpret_cast<int*>(c->ws + c->L.fid));
   for (int k = 0; k < 2; ++k)
     if (lens[k] > 0)
       hipLaunchKernelGGL(k_gather_info, dim3((lens[k] + tb - 1) / tb), dim3(tb), 0, c->stream, info,
@@ -443,7 +455,8 @@ lbm_status launch_init(lbm_ctx* c, const uint8_t* d_solid, const uint8_t* d_reac
   c->nb_ext = rounded_blocks(c->next);
   // The initial state goes into buffer 0 (make_args with src 1 writes buffer 0).
   StepArgs<P> A = make_args<P>(c, 1);
-  hipLaunchKernelGGL(k_init_state<P>, dim3(gb), dim3(tb), 0, c->stream, A, d_rr, d_rp, d_c0);
+  if (c->nfluid > 0)
+    hipLaunchKernelGGL(k_init_state<P>, dim3((c->nfluid + tb - 1) / tb), dim3(tb), 0, c->stream, A, d_rr, d_rp, d_c0);
   HIP_TRY(c, hipGetLastError());
   c->cur = 0;
   return LBM_OK;

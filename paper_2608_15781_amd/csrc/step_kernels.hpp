@@ -1,5 +1,11 @@
 // Forward kernels of one time step (HIP, gfx950).
 //
+// Storage. The state arrays hold fluid nodes only, indexed by fluid id (the rank of the node
+// among fluid nodes in node order, so rows stay contiguous); thread t of a launch is fluid node t
+// and writes its own slot, which makes every store a full coalesced line. Pulls find the id of
+// the source node through a dense node -> id map. The small per-node fields (rho^N, n*, wetting
+// data) stay dense, because the stencils also read them at solid nodes.
+//
 // State representation. Under Latva-Kokko recolouring of the colour-blind post-collision
 // populations (eq. operator_recoloring) followed by the proportional wall-reaction transfer,
 // the two colours' post-collision populations at a node are always
@@ -9,9 +15,10 @@
 // per-node scalars (a, v) (arithmetic precision) and, with the species, 7 populations g: 30
 // values per node instead of 45. Pulling f^r_i from node x - c_i reads f^m_i and (a, v) there.
 //
-// Layout: structure of arrays, one plane of N values per population or scalar, node index
-// x + nx*(y + ny*z) (x fastest). Two state buffers are used alternately (pull from one, write
-// the other), so no kernel reads what another thread of the same launch writes.
+// Layout: structure of arrays, one plane per population, fluid ids in node order (x fastest);
+// the colour scalars (a, v) as one 4-vector per fluid node. Two state buffers are used
+// alternately (pull from one, write the other), so no kernel reads what another thread of the
+// same launch writes.
 //
 // One step is four launches (each one thread per node):
 //   colour   pull f^m, a, v -> rho^N at fluid nodes             (eqs. moments_components, color_function)
@@ -108,6 +115,7 @@ struct StepArgs {
   const int* ext;         // dense indices of the solid nodes whose colour is extrapolated
   const uint32_t* einfo;  // their info words
   int next;
+  const int* fid;         // dense node -> fluid id (index into the state arrays), -1 for solid
   const uint32_t* info;
   // state in (pull source) and out
   const S* fin;  // 19 planes f^m
@@ -154,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     const bool bb = (i < 18) && ((inf >> i) & 1u);
-    const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+    const int src = bb ? t : A.fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
     const int q = bb ? D::opp[i] : i;
     const R sgn = bb ? R(-1) : R(1);  // c_q = sgn * c_i
     const R fm = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
@@ -374,11 +382,14 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
     const size_t N = A.N;
     // All loads of the node first (pull of f^m and g with halfway bounce-back, rho^N, the node's
     // and its neighbours' realigned normals), so that one memory round trip covers them.
+    int sid[18];  // fluid ids of the pull sources (own id for bounce-back)
+#pragma unroll
+    for (int i = 0; i < 18; ++i) sid[i] = ((inf >> i) & 1u) ? t : A.fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
     R f[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
       const bool bb = (i < 18) && ((inf >> i) & 1u);
-      const int src = bb ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+      const int src = (i < 18) ? sid[i] : t;
       const int q = bb ? D::opp[i] : i;
       f[i] = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
     }
@@ -389,11 +400,11 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
       for (int i = 0; i < 6; ++i) {
         const bool own = (i == 1 && outlet);  // zero-gradient outflow: the node's own S_1
         const bool bb = !own && ((inf >> i) & 1u);
-        const int src = (own || bb) ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+        const int src = own ? t : sid[i];
         const int q = own ? 1 : (bb ? D3Q7::opp[i] : i);
         g[i] = Prec<P>::ld(A.gin[size_t(q) * N + src], R(D3Q7::w(i)), A.inv_gscale);
       }
-      g[6] = Prec<P>::ld(A.gin[6 * N + n], R(D3Q7::w(6)), A.inv_gscale);
+      g[6] = Prec<P>::ld(A.gin[6 * N + t], R(D3Q7::w(6)), A.inv_gscale);
     }
     const R rn = A.rhoN[n];
     const typename V4<R>::T nsv = ld4(A.nst, n);
@@ -523,8 +534,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
       const R vc = keep * A.beta * rr * rp * irm;
       const R v0 = has_n ? vc * n0 : R(0), v1 = has_n ? vc * n1 : R(0), v2 = has_n ? vc * n2 : R(0);
 #pragma unroll
-      for (int i = 0; i < 19; ++i) A.fout[size_t(i) * N + n] = Prec<P>::st(fs[i], R(D::w(i)), A.scale);
-      st4(A.aout, n, aout, v0, v1, v2);
+      for (int i = 0; i < 19; ++i) A.fout[size_t(i) * N + t] = Prec<P>::st(fs[i], R(D::w(i)), A.scale);
+      st4(A.aout, t, aout, v0, v1, v2);
       bool ok = finite(fsum) && finite(aout) && finite(v0 + v1 + v2) && finite(rr) && finite(rp);
       if (A.species) {
         // BGK towards g^eq = w C (1 + 4 c.u_phys); at the inlet the populations are replaced by
@@ -539,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
           const R gi = inlet ? geq : g[i];
           const R go = (gi + (geq - gi) * A.inv_tau_c) * sink;
           gs += go;
-          A.gout[size_t(i) * N + n] = Prec<P>::st(go, R(D3Q7::w(i)), A.gscale);
+          A.gout[size_t(i) * N + t] = Prec<P>::st(go, R(D3Q7::w(i)), A.gscale);
         }
         ok = ok && finite(gs);
       }
@@ -564,14 +575,15 @@ __global__ __launch_bounds__(kBlock) void k_expand(StepArgs<P> A, typename Prec<
   const int n = logical_block() * kBlock + threadIdx.x;
   if (n >= A.N) return;
   const size_t N = A.N;
-  const bool fluid = A.info[n] & kFluid;
+  const int fi = A.fid[n];
+  const bool fluid = fi >= 0;
   typename V4<R>::T av;
   av.x = av.y = av.z = av.w = R(0);
-  if (fluid) av = ld4(A.ain, n);
+  if (fluid) av = ld4(A.ain, fi);
   const R a = av.x, v0 = av.y, v1 = av.z, v2 = av.w;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    R fm = fluid ? Prec<P>::ld(A.fin[size_t(i) * N + n], R(D::w(i)), A.inv_scale) : R(0);
+    R fm = fluid ? Prec<P>::ld(A.fin[size_t(i) * N + fi], R(D::w(i)), A.inv_scale) : R(0);
     R cv = R(D::cx[i]) * v0 + R(D::cy[i]) * v1 + R(D::cz[i]) * v2;
     R r = fluid ? a * fm + R(D::w_over_len(i)) * cv : R(0);
     fr[size_t(i) * N + n] = r;
@@ -580,7 +592,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(StepArgs<P> A, typename Prec<
   if (go) {
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-      go[size_t(i) * N + n] = (fluid && A.species) ? Prec<P>::ld(A.gin[size_t(i) * N + n], R(D3Q7::w(i)), A.inv_gscale) : R(0);
+      go[size_t(i) * N + n] = (fluid && A.species) ? Prec<P>::ld(A.gin[size_t(i) * N + fi], R(D3Q7::w(i)), A.inv_gscale) : R(0);
   }
 }
 
