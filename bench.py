@@ -9,6 +9,10 @@ FP16 / BF16 deviation storage with FP32 arithmetic; errors of each after the tim
 an FP64 run of the same library. One step = one pass of the whole step over the lattice; the
 state is resident in HBM before the timed region starts.
 
+Adjoint: 96^3 mask (wavelength 12, seed 4), contact angles 90 +- 10 degrees per node, 200 FP32
+steps with a checkpoint every 20; the backward pass (recompute + adjoint steps) of the gas
+production L = m^p(200) - m^p(0) is timed, and its gradients are compared with the FP64 ones.
+
 Prints one JSON line. value = million fluid-node updates per second (MFLUPS).
 """
 import argparse
@@ -43,6 +47,27 @@ def bytes_per_fluid_update(precision):
     return dict(colour=colour, normal=normal, collide=collide, step_min=step_min, naive45=naive)
 
 
+def measured_traffic(precision, kernel):
+    """Calibrated HBM bytes per launch of a kernel from the committed counter summary, or None.
+
+    The summary records the hash of the HIP sources it was taken on; a different hash means the
+    kernels changed since, and the figure no longer applies.
+    """
+    path = os.path.join(ROOT, "profiles", "step_kernels_bijel128_%s.md" % precision)
+    if not os.path.exists(path):
+        return None
+    from paper_2608_15781_amd import build as lbm_build
+
+    digest, val = None, None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- source_digest: "):
+                digest = line.split(": ", 1)[1].strip()
+            elif line.startswith("- traffic_bytes_per_launch %s: " % kernel):
+                val = float(line.rsplit(": ", 1)[1])
+    return val if digest == lbm_build.source_digest() else None
+
+
 def make_inputs(device):
     from paper_2608_15781_amd import inputs
 
@@ -74,6 +99,27 @@ def run_mode(core, torch, w, solid, theta, rr0, rp0, precision, steps, warmup, p
     return sim, red, dt, kern
 
 
+def adjoint_mode(core, torch, precision):
+    """Forward + checkpointed backward of the gas production on the 96^3 adjoint workload."""
+    from paper_2608_15781_amd import autograd as ag
+    from paper_2608_15781_amd import inputs
+
+    w, solid, theta, rr0, rp0 = inputs.workload_inputs("adjoint96", device="cuda:0")
+    steps, ck = w["steps"], w["checkpoint"]
+    sim = core.Lbm(w["shape"], solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision=precision,
+                   **sim_kwargs(w))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L, cps, final = ag.forward_states(sim, steps, ck)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gth, gxi, _ = ag.adjoint_gradients(sim, steps, ck, cps, final)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    nfluid = int((solid == 0).sum())
+    return dict(nfluid=nfluid, steps=steps, L=L, gth=gth, gxi=float(gxi), fwd_s=t1 - t0, bwd_s=t2 - t1)
+
+
 def rel_l2(a, b):
     a = a.double()
     b = b.double()
@@ -98,7 +144,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="fp16,bf16", help="extra storage precisions to time")
     args = ap.parse_args()
@@ -156,20 +203,29 @@ def main():
         del sim
     del sim64
 
+    adjoint = None
+    if not args.no_adjoint:
+        print("bench: adjoint (96^3, 200 steps, checkpoint 20), fp32 and fp64", file=sys.stderr, flush=True)
+        a32 = adjoint_mode(core, torch, "fp32")
+        a64 = adjoint_mode(core, torch, "fp64")
+        adjoint = dict(
+            workload="96^3 porous GRF mask (wavelength 12, seed 4), theta 90 +- 10 deg per node, %d steps, "
+                     "checkpoint every 20, dL/dtheta and dL/dxi of the gas production" % a32["steps"],
+            fluid_nodes=a32["nfluid"],
+            mflups=round(a32["nfluid"] * a32["steps"] / a32["bwd_s"] / 1e6, 1),
+            mflups_forward_with_checkpoints=round(a32["nfluid"] * a32["steps"] / a32["fwd_s"] / 1e6, 1),
+            backward_s=round(a32["bwd_s"], 4), forward_s=round(a32["fwd_s"], 4),
+            fp64_backward_s=round(a64["bwd_s"], 4),
+            error_vs_fp64=dict(L=abs(a32["L"] - a64["L"]) / abs(a64["L"]), dtheta=rel_l2(a32["gth"], a64["gth"]),
+                               dxi=abs(a32["gxi"] - a64["gxi"]) / abs(a64["gxi"])))
+        del a32, a64
+
     cpu = None
     if not args.no_cpu:
         print("bench: cpu baseline (oracle, %d steps)" % args.cpu_steps, file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, solid, theta, rr0, rp0, nfluid, args.cpu_steps)
 
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "collide_bijel128_fp32_traffic.json")
-    if os.path.exists(tpath):
-        with open(tpath) as f:
-            t = json.load(f)
-        from paper_2608_15781_amd import build as lbm_build
-
-        if t.get("source_digest") == lbm_build.source_digest():
-            traffic = t.get("bytes_per_launch")
+    traffic = measured_traffic("fp32", "lbm::k_collide<1, false>")
 
     out = {
         "metric": METRIC,
@@ -196,6 +252,7 @@ def main():
                           "naive45_bytes_per_fluid_update": b["naive45"],
                           "naive45_equiv_frac": round(mflups * 1e6 * b["naive45"] / (HBM_PEAK_GBS * 1e9), 4)},
         "modes": modes,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -9,8 +9,8 @@ Run under the profiler (the program itself follows ``--``):
 
 The driver runs the benchmark workload for the given number of steps, then a plain device-to-
 device copy of a known size (``--copy-mib``), whose counter readings calibrate the byte counters.
-``python3 -m paper_2608_15781_amd.profile_run summarize OUT`` turns the CSV files into the short
-text summary kept under ``profiles/``.
+``python3 -m paper_2608_15781_amd.profile_run report --precision P --fluid-nodes F TRACE FETCH WRITE``
+turns the three CSV folders into the short markdown summary kept under ``profiles/``.
 """
 from __future__ import annotations
 
@@ -52,40 +52,131 @@ def run(args):
 
 def _rows(pattern):
     out = []
-    for path in glob.glob(pattern, recursive=True):
+    for path in sorted(glob.glob(pattern, recursive=True)):
         with open(path) as f:
             out.extend(csv.DictReader(f))
     return out
 
 
-def summarize(out_dir, kernel="k_collide<1", copy_bytes=None):
-    """Average kernel durations and per-dispatch FETCH_SIZE / WRITE_SIZE (KiB), calibrated by the copy."""
-    res = {}
-    stats = _rows(os.path.join(out_dir, "**", "*kernel_stats.csv"))
-    res["kernels"] = {r["Name"]: dict(calls=int(r["Calls"]), avg_us=float(r["AverageNs"]) / 1e3) for r in stats}
+def _short(name):
+    """Kernel name without the return type and argument list."""
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def summarize(out_dir, copy_bytes):
+    """Average kernel durations, and per-dispatch FETCH_SIZE / WRITE_SIZE calibrated by the copy.
+
+    The calibration copy is the last dispatch of the run; its counters read (in KiB) what the
+    hardware reports for copy_bytes bytes read and written, and every kernel's counters are scaled
+    by copy_bytes / (1024 * that reading).
+    """
+    res = {"kernels": {}, "counters": {}}
+    for r in _rows(os.path.join(out_dir, "**", "*kernel_stats.csv")):
+        res["kernels"][_short(r["Name"])] = dict(calls=int(r["Calls"]), avg_us=float(r["AverageNs"]) / 1e3,
+                                                 min_us=float(r["MinNs"]) / 1e3, max_us=float(r["MaxNs"]) / 1e3)
     for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
-        rows = [r for r in _rows(os.path.join(out_dir, "**", "*counter_collection.csv")) if r.get("Counter_Name") == ctr]
+        rows = [r for r in _rows(os.path.join(out_dir, "**", "*counter_collection.csv"))
+                if r.get("Counter_Name") == ctr]
         if not rows:
             continue
-        per = {}
+        by_dispatch = {}
         for r in rows:
-            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        res[ctr] = {k: sum(v) / len(v) for k, v in per.items()}
+            key = int(r["Dispatch_Id"])
+            name, val = by_dispatch.get(key, (_short(r["Kernel_Name"]), 0.0))
+            by_dispatch[key] = (name, val + float(r["Counter_Value"]))
+        last = max(by_dispatch)
+        copy_kib = by_dispatch[last][1]
+        scale = copy_bytes / (1024.0 * copy_kib)
+        per = {}
+        for key, (name, val) in by_dispatch.items():
+            if key != last:
+                per.setdefault(name, []).append(val)
+        res["counters"][ctr] = dict(copy_kernel=by_dispatch[last][0], copy_kib=copy_kib, scale=scale,
+                                    kib_per_dispatch={k: sum(v) / len(v) for k, v in per.items()})
     return res
+
+
+def report(args):
+    """Markdown summary of one kernel-trace run and the FETCH_SIZE / WRITE_SIZE runs of a precision."""
+    sys.path.insert(0, ROOT)
+    from paper_2608_15781_amd import build
+
+    copy_bytes = args.copy_mib * (1 << 20)
+    kt = summarize(args.trace, copy_bytes)["kernels"]
+    fe = summarize(args.fetch, copy_bytes)["counters"]["FETCH_SIZE"]
+    wr = summarize(args.write, copy_bytes)["counters"]["WRITE_SIZE"]
+    fluid = args.fluid_nodes
+    lines = ["# Step kernels, %s, %s storage" % (args.workload, args.precision), "",
+             "Commands (repository root, `cd /tmp && export TMPDIR=/tmp` first, `PYTHONPATH` = repository root):", "",
+             "```",
+             "rocprofv3 --kernel-trace --stats --output-format csv -d OUT/prof -o run -- "
+             "python3 -m paper_2608_15781_amd.profile_run --precision %s --steps 50" % args.precision,
+             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o run -- "
+             "python3 -m paper_2608_15781_amd.profile_run --precision %s --steps 20" % args.precision,
+             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o run -- "
+             "python3 -m paper_2608_15781_amd.profile_run --precision %s --steps 20" % args.precision,
+             "python3 -m paper_2608_15781_amd.profile_run report --precision %s --fluid-nodes %d "
+             "OUT/prof OUT/fetch OUT/write" % (args.precision, fluid),
+             "```", "",
+             "Counter calibration: the run ends with a %d MiB device copy (source evicted from the last-level "
+             "cache first); it reads FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB for %.0f KiB moved each way, "
+             "so FETCH_SIZE is scaled by %.4f and WRITE_SIZE by %.4f." % (
+                 args.copy_mib, fe["copy_kib"], wr["copy_kib"], copy_bytes / 1024, fe["scale"], wr["scale"]), "",
+             "| kernel | calls | avg us | min us | FETCH KiB/dispatch | WRITE KiB/dispatch | HBM MB/launch "
+             "(calibrated) | B/fluid node | GB/s |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    traffic = {}
+    for name, k in sorted(kt.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["calls"]):
+        if not name.startswith("lbm::"):
+            continue
+        f = fe["kib_per_dispatch"].get(name)
+        w = wr["kib_per_dispatch"].get(name)
+        if f is None or w is None:
+            continue
+        b = 1024 * (f * fe["scale"] + w * wr["scale"])
+        traffic[name] = b
+        lines.append("| `%s` | %d | %.2f | %.2f | %.1f | %.1f | %.2f | %.1f | %.0f |" % (
+            name, k["calls"], k["avg_us"], k["min_us"], f, w, b / 1e6, b / fluid, b / (k["avg_us"] * 1e3)))
+    step_us = sum(k["avg_us"] for n, k in kt.items() if n.startswith("lbm::"))
+    step_b = sum(traffic.values())
+    lines += ["", "Fluid nodes: %d. Sum over the step kernels: %.2f us, %.1f MB, %.1f B per fluid node." % (
+        fluid, step_us, step_b / 1e6, step_b / fluid), "",
+        "Machine-readable (read by bench.py; valid only while the HIP sources hash to the digest):", "",
+        "- source_digest: %s" % build.source_digest()]
+    for name, b in traffic.items():
+        lines.append("- traffic_bytes_per_launch %s: %.0f" % (name, b))
+    print("\n".join(lines))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", nargs="?", default="run")
     ap.add_argument("out", nargs="?")
+    ap.add_argument("fetch", nargs="?")
+    ap.add_argument("write", nargs="?")
+    ap.add_argument("--fluid-nodes", type=int, default=0)
     ap.add_argument("--workload", default="bijel128")
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=512)
-    args = ap.parse_args()
+    args = ap.parse_intermixed_args()
     if args.cmd == "summarize":
-        print(json.dumps(summarize(args.out), indent=1))
+        print(json.dumps(summarize(args.out, args.copy_mib * (1 << 20)), indent=1))
+    elif args.cmd == "report":
+        args.trace = args.out
+        report(args)
     else:
         run(args)
 
