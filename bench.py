@@ -89,6 +89,7 @@ def run_mode(core, torch, w, solid, theta, rr0, rp0, precision, steps, warmup, p
     red = sim.step(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    mom = {k: v.clone() for k, v in sim.moments().items()}  # fields after warmup + steps
     kern = None
     if profile:
         sim.set_profiling(True)
@@ -144,7 +145,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="fp16,bf16", help="extra storage precisions to time")
@@ -166,7 +167,7 @@ def main():
     nall = nx * ny * nz
 
     print("bench: fp32 headline, %d warmup + %d timed steps" % (args.warmup, args.steps), file=sys.stderr, flush=True)
-    sim32, red32, dt32, kern32 = run_mode(core, torch, w, solid, theta, rr0, rp0, "fp32", args.steps, args.warmup,
+    sim32, red32, dt32, kern32, mom32 = run_mode(core, torch, w, solid, theta, rr0, rp0, "fp32", args.steps, args.warmup,
                                           profile=True)
     mflups = nfluid * args.steps / dt32 / 1e6
     ms_step = dt32 * 1e3 / args.steps
@@ -176,29 +177,27 @@ def main():
 
     # Reference: the same steps in FP64 storage and arithmetic.
     print("bench: fp64 reference run", file=sys.stderr, flush=True)
-    sim64, red64, dt64, _ = run_mode(core, torch, w, solid, theta, rr0, rp0, "fp64", args.steps, args.warmup,
+    sim64, red64, dt64, _, m64 = run_mode(core, torch, w, solid, theta, rr0, rp0, "fp64", args.steps, args.warmup,
                                      profile=False)
-    m64 = sim64.moments()
     conv64 = red64[:, 2].sum()
 
-    def errors(sim, red):
-        m = sim.moments()
+    def errors(m, red):
         rm = m["rho_r"] + m["rho_p"]
         rm64 = m64["rho_r"] + m64["rho_p"]
         return dict(rho_m=rel_l2(rm, rm64), u=rel_l2(m["u"], m64["u"]), rho_n=rel_l2(m["rho_n"], m64["rho_n"]),
                     c=rel_l2(m["c"], m64["c"]), conversion=float(abs(red[:, 2].sum() - conv64) / conv64))
 
-    err32 = errors(sim32, red32)
+    err32 = errors(mom32, red32)
     modes = {"fp32": dict(mflups=mflups, ms_per_step=ms_step, error_vs_fp64=err32, kernel_ms=kern32),
              "fp64": dict(mflups=nfluid * args.steps / dt64 / 1e6, ms_per_step=dt64 * 1e3 / args.steps)}
     del sim32
     for prec in [m for m in args.modes.split(",") if m]:
         print("bench: %s mode" % prec, file=sys.stderr, flush=True)
-        sim, red, dt, kern = run_mode(core, torch, w, solid, theta, rr0, rp0, prec, args.steps, args.warmup,
-                                      profile=True)
+        sim, red, dt, kern, mom = run_mode(core, torch, w, solid, theta, rr0, rp0, prec, args.steps, args.warmup,
+                                           profile=True)
         bp = bytes_per_fluid_update(prec)
         modes[prec] = dict(mflups=nfluid * args.steps / dt / 1e6, ms_per_step=dt * 1e3 / args.steps,
-                           error_vs_fp64=errors(sim, red), kernel_ms=kern,
+                           error_vs_fp64=errors(mom, red), kernel_ms=kern,
                            collide_gbs=bp["collide"] * nfluid / (kern["collide"] * 1e-3) / 1e9)
         del sim
     del sim64

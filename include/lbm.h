@@ -136,9 +136,11 @@ lbm_status lbm_populations(lbm_ctx* ctx, void* d_fr, void* d_fp, void* d_g);
 lbm_status lbm_geometry(lbm_ctx* ctx, void* d_info, void* d_wet);
 
 /* Byte offsets inside a state snapshot of its three parts: the 19 colour-blind population
- * planes (storage type, population-major [i*N + f]), the colour scalars as one 4-vector per node
- * (a, v_x, v_y, v_z; real type, [4*f + k]) and the 7 species planes (storage type; absent
- * without species). The state holds fluid nodes only: f is the fluid id, the rank of the node
+ * planes f^m (storage type, population-major [i*N + f]), the colour scalars as one 4-vector per
+ * node (e, v_x, v_y, v_z; real type, [4*f + k]) and the 7 species planes (storage type; absent
+ * without species). The per-colour populations are f^r_i = a f^m_i + (w_i/|c_i|) c_i.v and
+ * f^p_i = b f^m_i - (w_i/|c_i|) c_i.v with a + b = 1; e holds the smaller of a and b at full
+ * precision: e = -b when the sign bit of e is set (e = -0: pure reactant colour), else e = a. The state holds fluid nodes only: f is the fluid id, the rank of the node
  * among the fluid nodes in node order (0 .. nfluid-1); entries f >= nfluid are unused. In the *_DEV storages a
  * population f is stored as (f - w_i) * 2^k (k = fp16_scale_log2 for FP16, 0 for BF16). */
 lbm_status lbm_state_layout(const lbm_params* params, size_t* f_off, size_t* a_off, size_t* g_off);
@@ -160,8 +162,9 @@ lbm_status lbm_kernel_times(lbm_ctx* ctx, double* kernel_ms, int64_t* steps);
  * (eqs. product_mass, production_rate) with respect to the per-node contact angle theta(x)
  * (eq. realigned_normal_vectors) and the reaction rate xi (eq. reactive_boundary_condition_*).
  * An adjoint state holds 30 planes of N reals (context's real type), in the order of the state:
- * 19 colour-blind populations, the colour fraction a, the three components of the recolouring
- * vector v, 7 species populations, each plane indexed by fluid id like the state (entries
+ * 19 colour-blind populations, the colour fraction a (dL/da; e moves with a, de/da = 1 on
+ * either side of its sign), the three components of the recolouring vector v, 7 species
+ * populations, each plane indexed by fluid id like the state (entries
  * f >= nfluid are zero). lbm_adjoint_bytes gives its size and the size of the scratch buffer
  * lbm_adjoint_step needs (both caller-owned device memory). */
 lbm_status lbm_adjoint_bytes(const lbm_params* params, size_t* adj_bytes, size_t* scratch_bytes);

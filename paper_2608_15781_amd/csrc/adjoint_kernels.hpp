@@ -76,7 +76,7 @@ __device__ inline void cm_back_vjp(const R in[8], const R ld[19], R out[8]) {
 
 // ---------------------------------------------------------------------------------------------
 // Seed for L = m^p(T) = sum over fluid nodes and directions of the product populations of S_T:
-// sum_i S^p_i = (1 - a) sum_i f^m_i (the v term cancels by lattice symmetry).
+// sum_i S^p_i = b sum_i f^m_i with b = 1 - a (the v term cancels by lattice symmetry).
 // ---------------------------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_adj_seed(StepArgs<P> A, typename Prec<P>::R* lout) {
@@ -85,12 +85,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(StepArgs<P> A, typename Pre
   const int t = logical_block() * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const size_t N = A.N;
-  const R a = ld4(A.ain, t).x;
+  R a, b;
+  unpack_frac(ld4(A.ain, t).x, a, b);
   R s = 0;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     s += Prec<P>::ld(A.fin[size_t(i) * N + t], R(D::w(i)), A.inv_scale);
-    lout[size_t(i) * N + t] = R(1) - a;
+    lout[size_t(i) * N + t] = b;
   }
   lout[size_t(kAdjA) * N + t] = -s;
 }
@@ -136,9 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     }
     const R irm = R(1) / rm;
     const R ux = mx * irm, uy = my * irm, uz = mz * irm;
-    const R rn = A.rhoN[n];
-    const R rr = R(0.5) * rm * (R(1) + rn);
-    const R rp = R(0.5) * rm * (R(1) - rn);
+    R rr, rp;
+    rn_densities(A.rhoN[n], rm, rr, rp);
     const typename V4<R>::T nsv = ld4(A.nst, n);
     const R nn[3] = {nsv.x, nsv.y, nsv.z};
     const R glen = nsv.w;
@@ -379,8 +379,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
 #pragma unroll
     for (int a = 0; a < 3; ++a) l_m[a] = l_u[a] * irm;
     l_rm += -(l_u[0] * ux + l_u[1] * uy + l_u[2] * uz) * irm;
-    // rho^r, rho^p from rho^m and rho^N
-    l_rm += R(0.5) * (R(1) + rn) * l_rr + R(0.5) * (R(1) - rn) * l_rp;
+    // rho^r = rho^m (1 + rho^N)/2, rho^p = rho^m (1 - rho^N)/2
+    l_rm += rr * irm * l_rr + rp * irm * l_rp;
     const R l_rn = R(0.5) * rm * (l_rr - l_rp);
     if (A.species && !inlet)
 #pragma unroll
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     const int p = D::half[j];
-    const R d = A.rhoN[nb.at(D::cx[p], D::cy[p], D::cz[p])] - A.rhoN[nb.at(-D::cx[p], -D::cy[p], -D::cz[p])];
+    const R d = rn_diff(A.rhoN[nb.at(D::cx[p], D::cy[p], D::cz[p])], A.rhoN[nb.at(-D::cx[p], -D::cy[p], -D::cz[p])]);
     const R c3w = R(3.0 * D::w(p));
     if (D::cx[p]) g[0] += c3w * R(D::cx[p]) * d;
     if (D::cy[p]) g[1] += c3w * R(D::cy[p]) * d;
@@ -539,7 +539,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(StepArgs<P> A, AdjArgs<type
 
 // ---------------------------------------------------------------------------------------------
 // Transpose of the extrapolation rho^N(y) = sum_j w_j rho^N(y + c_j) / den(y) into the fluid node
-// z = y + c_j, then rho^N = (2 rho^r - rho^m)/rho^m reversed to d/d rho^r and d/d rho^m.
+// z = y + c_j, then rho^N = (2 rho^r - rho^m)/rho^m reversed to d/d rho^r and d/d rho^m (the
+// colour pass forms rho^N from rho^r and rho^p = rho^m - rho^r separately; the same function).
 // ---------------------------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_adj_colour(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
@@ -563,9 +564,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_colour(StepArgs<P> A, AdjArgs<ty
     l += R(D::w(j)) / den * J.lrn[y];
   }
   const R rm = J.rmv[n];
-  const R rn = A.rhoN[n];
+  const R q = A.rhoN[n];
+  const R one_plus_rn = signbit(q) ? R(2) + q : q;  // 1 + rho^N = 2 rho^r / rho^m
   J.lrr[n] = R(2) * l / rm;
-  J.lrm[n] = -(R(1) + rn) * l / rm;
+  J.lrm[n] = -one_plus_rn * l / rm;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -583,7 +585,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_final(StepArgs<P> A, AdjArgs<typ
   const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
-  const R a = ld4(A.ain, t).x;
+  R a, b;
+  unpack_frac(ld4(A.ain, t).x, a, b);
   R la = 0, lv[3] = {0, 0, 0};
 #pragma unroll
   for (int q = 0; q < 19; ++q) {

@@ -238,7 +238,7 @@ __global__ void k_init_state(StepArgs<P> A, const double* rr0, const double* rp0
   const size_t N = A.N;
   const double rm = rr0[n] + rp0[n];
   for (int i = 0; i < 19; ++i) A.fout[size_t(i) * N + t] = Prec<P>::st(R(D::w(i) * rm), R(D::w(i)), A.scale);
-  st4(A.aout, t, R(rr0[n] / rm), R(0), R(0), R(0));
+  st4(A.aout, t, R(pack_frac(rr0[n] / rm, rp0[n] / rm)), R(0), R(0), R(0));
   if (A.species) {
     const double c = c0 ? c0[n] : 1.0;
     for (int i = 0; i < 7; ++i) A.gout[size_t(i) * N + t] = Prec<P>::st(R(D3Q7::w(i) * c), R(D3Q7::w(i)), A.gscale);

@@ -9,11 +9,20 @@
 // State representation. Under Latva-Kokko recolouring of the colour-blind post-collision
 // populations (eq. operator_recoloring) followed by the proportional wall-reaction transfer,
 // the two colours' post-collision populations at a node are always
-//     f^r_i = a f^m_i + (w_i/|c_i|) c_i . v,     f^p_i = f^m_i - f^r_i,
-// with a = (1 - phi) rho^r / rho^m and v = (1 - phi) beta (rho^r rho^p / rho^m) n*. The state is
-// therefore stored exactly as the 19 colour-blind populations f^m (storage precision), the four
-// per-node scalars (a, v) (arithmetic precision) and, with the species, 7 populations g: 30
-// values per node instead of 45. Pulling f^r_i from node x - c_i reads f^m_i and (a, v) there.
+//     f^r_i = a f^m_i + (w_i/|c_i|) c_i . v,     f^p_i = b f^m_i - (w_i/|c_i|) c_i . v,
+// with a = (1 - phi) rho^r / rho^m, b = 1 - a and v = (1 - phi) beta (rho^r rho^p / rho^m) n*. The
+// state is therefore stored exactly as the 19 colour-blind populations f^m (storage precision),
+// the four per-node scalars (a or b, v) (arithmetic precision) and, with the species, 7
+// populations g: 30 values per node instead of 45. Pulling f^r_i from node x - c_i reads f^m_i
+// and the scalars there.
+//
+// Near-pure phases. Where one colour is a trace (gas nucleating at a wall, a liquid film inside
+// a bubble), storing a next to 1 or rho^N next to +-1 would round the trace colour to the
+// absolute precision of the arithmetic type (6e-8 in FP32), and the interface normal, which
+// divides by a gradient that may be as small as 1e-6, would be noise. Both are therefore kept
+// in a minority form (pack_frac, rn_diff below): the smaller member of each pair (a, b) and
+// ((1 + rho^N)/2, (1 - rho^N)/2) is stored at full relative precision, the sign bit telling
+// which one it is. Colour densities and gradients of rho^N are formed from those directly.
 //
 // Layout: structure of arrays, one plane per population, fluid ids in node order (x fastest);
 // the colour scalars (a, v) as one 4-vector per fluid node. Two state buffers are used
@@ -54,6 +63,49 @@ __device__ inline void st4(R* p, size_t n, R x, R y, R z, R w) {
   v.x = x; v.y = y; v.z = z; v.w = w;
   reinterpret_cast<typename V4<R>::T*>(p)[n] = v;
 }  // MI355X: 8 XCDs; workgroups are dealt round-robin across them
+
+// A pair of colour fractions (a, b), a + b = 1, stored as one number that holds the smaller one
+// to full relative precision: e = -|b| (sign bit set) when 0 <= b <= a or a < 0, else e = |a|.
+// So e = -0 is the pure reactant (red) state and e = +0 the pure product (blue) state; values
+// outside [0, 1] (a colour density that rounded below zero) keep their sign consistently.
+template <class R>
+__device__ inline R pack_frac(R a, R b) {
+  const bool minor_b = (b <= a && b >= R(0)) || a < R(0);
+  return minor_b ? -fabs(b) : fabs(a);
+}
+template <class R>
+__device__ inline void unpack_frac(R e, R& a, R& b) {
+  if (signbit(e)) {
+    b = -e;
+    a = R(1) - b;
+  } else {
+    a = e;
+    b = R(1) - a;
+  }
+}
+// rho^N = a - b is stored as q = rho^N - s with s = +1 if the sign bit of q is set (product
+// colour in the minority, q = -2b) and s = -1 otherwise (q = 2a).
+template <class R>
+__device__ inline R rn_side(R q) { return signbit(q) ? R(1) : R(-1); }
+template <class R>
+__device__ inline R rn_value(R q) { return q + rn_side(q); }
+// rho^N(x) - rho^N(y) without the cancellation of two values next to +-1.
+template <class R>
+__device__ inline R rn_diff(R qx, R qy) { return (qx - qy) + (rn_side(qx) - rn_side(qy)); }
+// q from the colour densities (rm = rho^r + rho^p up to rounding).
+template <class R>
+__device__ inline R rn_pack(R rr, R rp, R irm) { return R(2) * pack_frac(rr * irm, rp * irm); }
+// rho^r and rho^p at a node from q and rho^m, the minority one directly.
+template <class R>
+__device__ inline void rn_densities(R q, R rm, R& rr, R& rp) {
+  if (signbit(q)) {
+    rp = R(-0.5) * q * rm;
+    rr = rm - rp;
+  } else {
+    rr = R(0.5) * q * rm;
+    rp = rm - rr;
+  }
+}
 
 // Maps the hardware workgroup id to a logical tile so that each XCD (with its own L2) works on
 // one contiguous slab of the lattice; neighbouring rows then share that XCD's L2.
@@ -119,12 +171,12 @@ struct StepArgs {
   const uint32_t* info;
   // state in (pull source) and out
   const S* fin;  // 19 planes f^m
-  const R* ain;  // per node 4-vector (a, vx, vy, vz)
+  const R* ain;  // per node 4-vector (e, vx, vy, vz), e = pack_frac(a, b)
   const S* gin;  // 7 planes species
   S* fout;
   R* aout;
   S* gout;
-  R* rhoN;       // 1 plane
+  R* rhoN;       // 1 plane, rho^N in the form of rn_value
   R* rm_out;     // optional: rho^m of each fluid node (adjoint recompute)
   R* nst;        // per node 4-vector (n*_x, n*_y, n*_z, |grad rho^N|)
   const R* wet;  // per node 4-vector (n_s, cos(theta))
@@ -158,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
   const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
-  R rm = 0, rr = 0;
+  R rm = 0, rr = 0, rp = 0;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     const bool bb = (i < 18) && ((inf >> i) & 1u);
@@ -171,11 +223,14 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
     if (D::cx[i]) cv += R(D::cx[i]) * av.y;
     if (D::cy[i]) cv += R(D::cy[i]) * av.z;
     if (D::cz[i]) cv += R(D::cz[i]) * av.w;
-    const R a = av.x;
+    R a, b;
+    unpack_frac(av.x, a, b);
+    const R kv = R(D::w_over_len(i)) * sgn * cv;
     rm += fm;
-    rr += a * fm + R(D::w_over_len(i)) * sgn * cv;
+    rr += a * fm + kv;
+    rp += b * fm - kv;
   }
-  A.rhoN[n] = (rr + rr - rm) / rm;
+  A.rhoN[n] = rn_pack(rr, rp, R(1) / rm);
   if (A.rm_out) A.rm_out[n] = rm;
 }
 
@@ -191,15 +246,24 @@ __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs<P> A) {
   const int n = A.ext[t];
   const uint32_t inf = A.einfo[t];
   const Nbr nb = make_nbr(n, A.geo);
-  R num = 0, den = 0;
+  // Weighted sums of the offsets q and of the sides s separately; -0 as the start keeps the
+  // sign of an all-(-0) sum.
+  R nq = R(-0.0), ns = 0, den = 0;
 #pragma unroll
   for (int i = 0; i < 18; ++i) {
     if ((inf >> i) & 1u) {
-      num += R(D::w(i)) * A.rhoN[nb.at(D::cx[i], D::cy[i], D::cz[i])];
+      const R q = A.rhoN[nb.at(D::cx[i], D::cy[i], D::cz[i])];
+      nq += R(D::w(i)) * q;
+      ns += R(D::w(i)) * rn_side(q);
       den += R(D::w(i));
     }
   }
-  A.rhoN[n] = num / den;
+  if (ns == den || ns == -den) {
+    A.rhoN[n] = nq / den;  // all neighbours on one side: the average keeps that side
+  } else {
+    const R v = (ns + nq) / den;
+    A.rhoN[n] = R(2) * pack_frac(R(0.5) * (R(1) + v), R(0.5) * (R(1) - v));
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -221,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     const int p = D::half[j];
-    const R d = A.rhoN[nb.at(D::cx[p], D::cy[p], D::cz[p])] - A.rhoN[nb.at(-D::cx[p], -D::cy[p], -D::cz[p])];
+    const R d = rn_diff(A.rhoN[nb.at(D::cx[p], D::cy[p], D::cz[p])], A.rhoN[nb.at(-D::cx[p], -D::cy[p], -D::cz[p])]);
     const R c3w = R(3.0 * D::w(p));
     if (D::cx[p]) g[0] += c3w * R(D::cx[p]) * d;
     if (D::cy[p]) g[1] += c3w * R(D::cy[p]) * d;
@@ -430,8 +494,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
     }
     const R irm = R(1) / rm;
     const R ux = mx * irm, uy = my * irm, uz = mz * irm;
-    const R rr = R(0.5) * rm * (R(1) + rn);
-    const R rp = R(0.5) * rm * (R(1) - rn);
+    R rr, rp;
+    rn_densities(rn, rm, rr, rp);
 
     // Realigned unit normal and gradient magnitude; curvature H = -(tr J - n.J.n) with
     // J_ab = 3 sum_i w_i c_ib n*_a(x + c_i), a solid neighbour contributing n*(x).
@@ -477,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
     if (MOM) {
       if (A.m_rr) A.m_rr[n] = rr;
       if (A.m_rp) A.m_rp[n] = rp;
-      if (A.m_rn) A.m_rn[n] = rn;
+      if (A.m_rn) A.m_rn[n] = rn_value(rn);
       if (A.m_u) { A.m_u[n] = upx; A.m_u[N + n] = upy; A.m_u[2 * N + n] = upz; }
       if (A.m_c) A.m_c[n] = C;
     } else {
@@ -529,8 +593,9 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
         }
       }
       const R keep = (delta != R(0)) ? R(1) - delta / rr : R(1);
-      // Compact recoloured state: a = keep rho^r/rho^m, v = keep beta rho^r rho^p/rho^m n*.
-      const R aout = keep * rr * irm;
+      // Compact recoloured state: a = (rho^r - delta)/rho^m, b = (rho^p + delta)/rho^m,
+      // v = keep beta rho^r rho^p/rho^m n* with keep = 1 - delta/rho^r.
+      const R aout = pack_frac((rr - delta) * irm, (rp + delta) * irm);
       const R vc = keep * A.beta * rr * rp * irm;
       const R v0 = has_n ? vc * n0 : R(0), v1 = has_n ? vc * n1 : R(0), v2 = has_n ? vc * n2 : R(0);
 #pragma unroll
@@ -580,14 +645,15 @@ __global__ __launch_bounds__(kBlock) void k_expand(StepArgs<P> A, typename Prec<
   typename V4<R>::T av;
   av.x = av.y = av.z = av.w = R(0);
   if (fluid) av = ld4(A.ain, fi);
-  const R a = av.x, v0 = av.y, v1 = av.z, v2 = av.w;
+  const R v0 = av.y, v1 = av.z, v2 = av.w;
+  R a, b;
+  unpack_frac(av.x, a, b);
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    R fm = fluid ? Prec<P>::ld(A.fin[size_t(i) * N + fi], R(D::w(i)), A.inv_scale) : R(0);
-    R cv = R(D::cx[i]) * v0 + R(D::cy[i]) * v1 + R(D::cz[i]) * v2;
-    R r = fluid ? a * fm + R(D::w_over_len(i)) * cv : R(0);
-    fr[size_t(i) * N + n] = r;
-    fp[size_t(i) * N + n] = fm - r;
+    const R fm = fluid ? Prec<P>::ld(A.fin[size_t(i) * N + fi], R(D::w(i)), A.inv_scale) : R(0);
+    const R kv = R(D::w_over_len(i)) * (R(D::cx[i]) * v0 + R(D::cy[i]) * v1 + R(D::cz[i]) * v2);
+    fr[size_t(i) * N + n] = fluid ? a * fm + kv : R(0);
+    fp[size_t(i) * N + n] = fluid ? b * fm - kv : R(0);
   }
   if (go) {
 #pragma unroll

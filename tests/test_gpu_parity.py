@@ -209,6 +209,32 @@ def test_reduced_precision_against_fp64_reference(core, oracle_mod, precision, t
     _compare(gpu, ref, tol, "porous %s t=100" % precision)
 
 
+@pytest.mark.parametrize("minority", ["product", "reactant"])
+def test_fp32_trace_colour_against_oracle(core, oracle_mod, minority):
+    """A trace of one colour (1e-5) with a smooth profile: its density, its populations and the
+    interface normals built from its gradient (|grad rho^N| ~ 4e-6, just above the 1e-6 guard) must
+    keep FP32 relative precision in the trace colour itself, on either side of the encoding."""
+    shape = (16, 16, 16)
+    z, y, x = np.meshgrid(*(np.arange(k) for k in shape[::-1]), indexing="ij")
+    eps = 1e-5 * (1 + 0.5 * np.sin(2 * np.pi * x / 16) * np.sin(2 * np.pi * y / 16) + 0.3 * np.cos(2 * np.pi * z / 16))
+    rr0, rp0 = (1 - eps, eps) if minority == "product" else (eps, 1 - eps)
+    gpu, ref = _pair(core, oracle_mod, shape, rho_r0=rr0, rho_p0=rp0, precision="fp32", tau=0.8, sigma=0.01,
+                     beta=0.7)
+    gpu.step(20)
+    ref.step(20)
+    m = gpu.moments()
+    r = ref.moments()
+    trace = "rho_p" if minority == "product" else "rho_r"
+    fr, fp, _ = gpu.populations()
+    rfr, rfp, _ = ref.get_state()
+    tf = (fp if minority == "product" else fr).cpu().numpy()
+    rtf = rfp if minority == "product" else rfr
+    e_rho = _rel(m[trace].cpu().numpy(), r[trace])
+    e_pop = _rel(tf, rtf)
+    print("trace %s: %s %.2e populations %.2e" % (minority, trace, e_rho, e_pop), flush=True)
+    assert e_rho < 1e-5 and e_pop < 1e-5
+
+
 def test_checkpoint_roundtrip_and_determinism(core, oracle_mod):
     shape = (20, 20, 20)
     solid, theta, rr0, rp0 = _full_case(shape, seed=23)
