@@ -131,8 +131,8 @@ lbm_status lbm_populations(lbm_ctx* ctx, void* d_fr, void* d_fp, void* d_g);
  * bit i (i < 18) = node x - c_i is solid, bit 18 = fluid, bit 19 = wetting node (some
  * neighbour solid), bits 20..22 = r(x) * NN(x); at solid nodes bit i (i < 18) = node x + c_i
  * is fluid and bit 23 = colour is extrapolated into this node. d_wet (4N, real type, node-major
- * [4*n + k]): unit solid normal n_s (k = 0..2, zero where undefined) and cos(theta) (k = 3).
- * Either may be NULL. */
+ * [4*n + k]): at fluid nodes the unit solid normal n_s (k = 0..2, zero where undefined) and
+ * cos(theta) (k = 3); zero at solid nodes. Either may be NULL. */
 lbm_status lbm_geometry(lbm_ctx* ctx, void* d_info, void* d_wet);
 
 /* Byte offsets inside a state snapshot of its three parts: the 19 colour-blind population

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     const R ux = mx * irm, uy = my * irm, uz = mz * irm;
     R rr, rp;
     rn_densities(A.rhoN[n], rm, rr, rp);
-    const typename V4<R>::T nsv = ld4(A.nst, n);
+    const typename V4<R>::T nsv = ld4(A.nst, t);
     const R nn[3] = {nsv.x, nsv.y, nsv.z};
     const R glen = nsv.w;
     const bool has_n = glen > A.eps;
@@ -148,9 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     if (has_n) {
 #pragma unroll
       for (int i = 0; i < 18; ++i) {
-        const bool sol = (inf >> D::opp[i]) & 1u;
-        const int m = nb.at(D::cx[i], D::cy[i], D::cz[i]);
-        const typename V4<R>::T mv = sol ? nsv : ld4(A.nst, m);
+        const typename V4<R>::T mv = ld4(A.nst, sid[D::opp[i]]);  // own id where x + c_i is solid
         const R a0 = mv.x, a1 = mv.y, a2 = mv.z;
         const R w3 = R(3.0 * D::w(i));
         if (D::cx[i]) { Jm[0][0] += w3 * R(D::cx[i]) * a0; Jm[1][0] += w3 * R(D::cx[i]) * a1; Jm[2][0] += w3 * R(D::cx[i]) * a2; }
@@ -448,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
     const int m = nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
     const R lh = J.lH[m];
     if (lh == R(0)) continue;
-    const typename V4<R>::T qv = ld4(A.nst, m);
+    const typename V4<R>::T qv = ld4(A.nst, A.fid[m]);
     const R q0 = qv.x, q1 = qv.y, q2 = qv.z;
     const R cn = R(D::cx[i]) * q0 + R(D::cy[i]) * q1 + R(D::cz[i]) * q2;
     const R w3 = R(-3.0 * D::w(i)) * lh;
@@ -474,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
     const R nv[3] = {g[0] * il, g[1] * il, g[2] * il};
     R ln[3] = {mu[0], mu[1], mu[2]};
     if (inf & kWet) {
-      const typename V4<R>::T wv = ld4(A.wet, n);
+      const typename V4<R>::T wv = ld4(A.wet, t);
       const R sx = wv.x, sy = wv.y, sz = wv.z;
       if (sx * sx + sy * sy + sz * sz > R(0.5)) {
         const R ct = wv.w;

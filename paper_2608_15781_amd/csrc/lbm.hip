@@ -193,11 +193,11 @@ __global__ void k_init_info(int nx, int ny, int nz, const uint8_t* solid, const 
 // sum is accumulated exactly in integers (5040 w = 448, 240, 96, 50, 16, 8, 1) and normalised
 // once; a zero sum leaves n_s undefined (stored as 0). Also stores cos(theta).
 template <class R>
-__global__ void k_init_wet(int nx, int ny, int nz, const uint8_t* solid, const uint32_t* info, const double* theta,
-                           double theta_uniform, R* wet) {
+__global__ void k_init_wet(int nx, int ny, int nz, const uint8_t* solid, const uint32_t* info, const int* fid,
+                           const double* theta, double theta_uniform, R* wet) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   const int N = nx * ny * nz;
-  if (n >= N) return;
+  if (n >= N || !(info[n] & kFluid)) return;
   const int x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
   const double th = theta ? theta[n] : theta_uniform;
   long sx = 0, sy = 0, sz = 0;
@@ -224,7 +224,21 @@ __global__ void k_init_wet(int nx, int ny, int nz, const uint8_t* solid, const u
   }
   double len = sqrt(double(sx * sx + sy * sy + sz * sz));
   double il = len > 0 ? 1.0 / len : 0.0;
-  st4(wet, n, R(sx * il), R(sy * il), R(sz * il), R(cos(th)));
+  st4(wet, fid[n], R(sx * il), R(sy * il), R(sz * il), R(cos(th)));
+}
+
+// Dense copy (4 reals per node, node-major) of the per-fluid-id wetting data; zero at solids.
+template <class R>
+__global__ void k_wet_dense(int N, const int* fid, const R* wet, R* out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int f = fid[n];
+  if (f >= 0) {
+    const typename V4<R>::T v = ld4(wet, f);
+    st4(out, n, v.x, v.y, v.z, v.w);
+  } else {
+    st4(out, n, R(0), R(0), R(0), R(0));
+  }
 }
 
 // S_0 = f^eq(rho^k_0, 0) per colour: f^m = w (rho^r + rho^p), a = rho^r / rho^m, v = 0, g = w C_0.
@@ -367,7 +381,15 @@ StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
 template <int P>
 lbm_status launch_step(lbm_ctx* c, int slot) {
   StepArgs<P> A = make_args<P>(c, c->cur);
-  A.ring_row = reinterpret_cast<double*>(c->ws + c->L.ring) + 5 * size_t(slot);
+  double* ring = reinterpret_cast<double*>(c->ws + c->L.ring);
+  A.ring_row = ring + 5 * size_t(slot);
+  // The previous step's partials are summed by k_normal of this step (its workgroup 0); the
+  // last step of a chunk is summed by launch_finish.
+  A.red_in = A.partials;
+  A.red_n = c->nb_fluid;
+  A.red_out = slot > 0 ? ring + 5 * size_t(slot - 1) : nullptr;
+  if (A.red_out && !c->nb_fluid)
+    hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlock), 0, c->stream, A.partials, c->nb_fluid, A.red_out);
   const dim3 grid(c->L.nblocks), block(kBlock);
   const dim3 gf(c->nb_fluid), ge(c->nb_ext);
   hipEvent_t* ev = c->prof ? &c->ev[5 * size_t(slot)] : nullptr;
@@ -380,10 +402,18 @@ lbm_status launch_step(lbm_ctx* c, int slot) {
   if (ev) HIP_TRY(c, hipEventRecord(ev[3], c->stream));
   if (c->nb_fluid) hipLaunchKernelGGL((k_collide<P, false>), gf, block, 0, c->stream, A);
   if (ev) HIP_TRY(c, hipEventRecord(ev[4], c->stream));
-  hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kFinish), 0, c->stream, A.partials, c->nb_fluid, A.ring_row);
   HIP_TRY(c, hipGetLastError());
   c->cur = 1 - c->cur;
   c->steps++;
+  return LBM_OK;
+}
+
+// Final reduction of the last step of a chunk (ring row `slot`).
+lbm_status launch_finish(lbm_ctx* c, int slot) {
+  double* ring = reinterpret_cast<double*>(c->ws + c->L.ring);
+  hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlock), 0, c->stream,
+                     reinterpret_cast<const double*>(c->ws + c->L.partials), c->nb_fluid, ring + 5 * size_t(slot));
+  HIP_TRY(c, hipGetLastError());
   return LBM_OK;
 }
 
@@ -427,8 +457,6 @@ lbm_status launch_init(lbm_ctx* c, const uint8_t* d_solid, const uint8_t* d_reac
   uint32_t* info = reinterpret_cast<uint32_t*>(c->ws + c->L.info);
   hipLaunchKernelGGL(k_init_info, dim3(gb), dim3(tb), 0, c->stream, p.nx, p.ny, p.nz, d_solid, d_react,
                      int(p.species && p.x_open), info);
-  hipLaunchKernelGGL(k_init_wet<R>, dim3(gb), dim3(tb), 0, c->stream, p.nx, p.ny, p.nz, d_solid, info, d_theta,
-                     theta_uniform, reinterpret_cast<R*>(c->ws + c->L.wet));
   // Launch lists: fluid nodes and solid nodes with extrapolated colour, in node order.
   int* counts = reinterpret_cast<int*>(c->ws + c->L.counts);
   const uint32_t masks[2] = {kFluid, kExtrap};
@@ -446,6 +474,9 @@ lbm_status launch_init(lbm_ctx* c, const uint8_t* d_solid, const uint8_t* d_reac
   hipLaunchKernelGGL(k_fill_fid, dim3(gb), dim3(tb), 0, c->stream, info,
                      reinterpret_cast<const int*>(c->ws + c->L.lists[0]), c->N, c->nfluid,
                      reinterpret_cast<int*>(c->ws + c->L.fid));
+  hipLaunchKernelGGL(k_init_wet<R>, dim3(gb), dim3(tb), 0, c->stream, p.nx, p.ny, p.nz, d_solid, info,
+                     reinterpret_cast<const int*>(c->ws + c->L.fid), d_theta, theta_uniform,
+                     reinterpret_cast<R*>(c->ws + c->L.wet));
   for (int k = 0; k < 2; ++k)
     if (lens[k] > 0)
       hipLaunchKernelGGL(k_gather_info, dim3((lens[k] + tb - 1) / tb), dim3(tb), 0, c->stream, info,
@@ -521,7 +552,7 @@ lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* lin, void*
   HIP_TRY(c, hipMemsetAsync(lout, 0, AL.adj_bytes, c->stream));
   if (c->nb_fluid) {
     hipLaunchKernelGGL(k_adj_collide<P>, gf, block, 0, c->stream, A, J);
-    hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kFinish), 0, c->stream, J.partials, c->nb_fluid, sum);
+    hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlock), 0, c->stream, J.partials, c->nb_fluid, sum);
     hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, c->stream, sum, gxi);
     hipLaunchKernelGGL(k_adj_normal<P>, gf, block, 0, c->stream, A, J);
     hipLaunchKernelGGL((k_adj_grad<P, false>), gf, block, 0, c->stream, A, J);
@@ -676,6 +707,7 @@ lbm_status lbm_step(lbm_ctx* c, int32_t nsteps, lbm_reductions* per_step) {
       }
       if (s != LBM_OK) return s;
     }
+    if (lbm_status s = launch_finish(c, chunk - 1); s != LBM_OK) return s;
     rows.resize(5 * size_t(chunk));
     HIP_TRY(c, hipMemcpyAsync(rows.data(), c->ws + c->L.ring, rows.size() * sizeof(double), hipMemcpyDeviceToHost,
                               c->stream));
@@ -721,9 +753,17 @@ lbm_status lbm_geometry(lbm_ctx* c, void* d_info, void* d_wet) {
   if (!c) return LBM_ERR_ARG;
   const size_t N = c->N;
   if (d_info) HIP_TRY(c, hipMemcpyAsync(d_info, c->ws + c->L.info, 4 * N, hipMemcpyDeviceToDevice, c->stream));
-  if (d_wet)
-    HIP_TRY(c, hipMemcpyAsync(d_wet, c->ws + c->L.wet, 4 * real_bytes(c->p.precision) * N, hipMemcpyDeviceToDevice,
-                              c->stream));
+  if (d_wet) {
+    const int tb = 256, gb = int((N + tb - 1) / tb);
+    const int* fid = reinterpret_cast<const int*>(c->ws + c->L.fid);
+    if (c->p.precision == LBM_FP64)
+      hipLaunchKernelGGL(k_wet_dense<double>, dim3(gb), dim3(tb), 0, c->stream, int(N), fid,
+                         reinterpret_cast<const double*>(c->ws + c->L.wet), static_cast<double*>(d_wet));
+    else
+      hipLaunchKernelGGL(k_wet_dense<float>, dim3(gb), dim3(tb), 0, c->stream, int(N), fid,
+                         reinterpret_cast<const float*>(c->ws + c->L.wet), static_cast<float*>(d_wet));
+    HIP_TRY(c, hipGetLastError());
+  }
   return LBM_OK;
 }
 

@@ -178,10 +178,14 @@ struct StepArgs {
   S* gout;
   R* rhoN;       // 1 plane, rho^N in the form of rn_value
   R* rm_out;     // optional: rho^m of each fluid node (adjoint recompute)
-  R* nst;        // per node 4-vector (n*_x, n*_y, n*_z, |grad rho^N|)
-  const R* wet;  // per node 4-vector (n_s, cos(theta))
+  R* nst;        // per fluid id 4-vector (n*_x, n*_y, n*_z, |grad rho^N|)
+  const R* wet;  // per fluid id 4-vector (n_s, cos(theta))
   double* partials;
   double* ring_row;  // 5 doubles of this step
+  // Deferred final reduction of the previous step, done by workgroup 0 of k_normal (null: none)
+  const double* red_in;
+  int red_n;
+  double* red_out;
   R relax;           // 1 - 1/tau
   R inv_tau_c;
   R sigma, beta, xi, c_in, eps;
@@ -196,6 +200,50 @@ struct StepArgs {
   R* m_u;
   R* m_c;
 };
+
+// Sum of the per-workgroup partials (5 planes of nparts) by one workgroup of kBlock threads, in
+// a fixed order: strided per-thread sums, then wavefront shuffles, then the waves in order. Every
+// caller uses this one routine with the same thread count, so a step's sums do not depend on
+// where the reduction ran.
+__device__ inline void reduce_partials(const double* partials, int nparts, double* out) {
+  __shared__ double red[kBlock / 64][5];
+  double t[5] = {0, 0, 0, 0, 0};
+  int b = threadIdx.x;
+  for (; b + 3 * kBlock < nparts; b += 4 * kBlock) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const double* p = partials + size_t(j) * nparts;
+      t[j] += ((p[b] + p[b + kBlock]) + (p[b + 2 * kBlock] + p[b + 3 * kBlock]));
+    }
+  }
+  for (; b < nparts; b += kBlock) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) t[j] += partials[size_t(j) * nparts + b];
+  }
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t[j] += __shfl_xor(t[j], off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) red[wave][j] = t[j];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      double v = red[0][j];
+#pragma unroll
+      for (int w = 1; w < kBlock / 64; ++w) v += red[w][j];
+      out[j] = v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish_reduce(const double* partials, int nparts, double* out) {
+  reduce_partials(partials, nparts, out);
+}
 
 // ---------------------------------------------------------------------------------------------
 // colour: rho^N = (rho^r - rho^p)/rho^m from the pulled populations.
@@ -219,10 +267,8 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
     const R sgn = bb ? R(-1) : R(1);  // c_q = sgn * c_i
     const R fm = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
     const typename V4<R>::T av = ld4(A.ain, src);
-    R cv = 0;
-    if (D::cx[i]) cv += R(D::cx[i]) * av.y;
-    if (D::cy[i]) cv += R(D::cy[i]) * av.z;
-    if (D::cz[i]) cv += R(D::cz[i]) * av.w;
+    // all three products, zeros included, so that the 4-vector is fetched by one wide load
+    const R cv = R(D::cx[i]) * av.y + R(D::cy[i]) * av.z + R(D::cz[i]) * av.w;
     R a, b;
     unpack_frac(av.x, a, b);
     const R kv = R(D::w_over_len(i)) * sgn * cv;
@@ -276,6 +322,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
+  if (A.red_out && blockIdx.x == 0) reduce_partials(A.red_in, A.red_n, A.red_out);
   const int t = logical_block() * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
@@ -297,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
     const R il = R(1) / len;
     nv[0] = g[0] * il; nv[1] = g[1] * il; nv[2] = g[2] * il;
     if (inf & kWet) {
-      const typename V4<R>::T wv = ld4(A.wet, n);
+      const typename V4<R>::T wv = ld4(A.wet, t);
       const R sx = wv.x, sy = wv.y, sz = wv.z;
       if (sx * sx + sy * sy + sz * sz > R(0.5)) {
         const R ct = wv.w;
@@ -320,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
       }
     }
   }
-  st4(A.nst, n, nv[0], nv[1], nv[2], len);
+  st4(A.nst, t, nv[0], nv[1], nv[2], len);
 }
 
 // T^{-1} k* of Appendix A (eq. back_transformation_vector), regrouped with common
@@ -392,43 +439,6 @@ __device__ inline void block_reduce5(double s[5], double* partials) {
   }
 }
 
-constexpr int kFinish = 1024;
-
-__global__ __launch_bounds__(kFinish) void k_finish_reduce(const double* partials, int nparts, double* out) {
-  __shared__ double red[kFinish / 64][5];
-  double t[5] = {0, 0, 0, 0, 0};
-  int b = threadIdx.x;
-  for (; b + 3 * kFinish < nparts; b += 4 * kFinish) {
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      const double* p = partials + size_t(j) * nparts;
-      t[j] += ((p[b] + p[b + kFinish]) + (p[b + 2 * kFinish] + p[b + 3 * kFinish]));
-    }
-  }
-  for (; b < nparts; b += kFinish) {
-#pragma unroll
-    for (int j = 0; j < 5; ++j) t[j] += partials[size_t(j) * nparts + b];
-  }
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) t[j] += __shfl_xor(t[j], off, 64);
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int j = 0; j < 5; ++j) red[wave][j] = t[j];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      double v = red[0][j];
-      for (int w = 1; w < kFinish / 64; ++w) v += red[w][j];
-      out[j] = v;
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------------------------
 // collide: the rest of the step at every fluid node. MOM = true writes the level-t fields
 // instead (lbm_moments) and leaves the state untouched.
@@ -471,13 +481,12 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
       g[6] = Prec<P>::ld(A.gin[6 * N + t], R(D3Q7::w(6)), A.inv_gscale);
     }
     const R rn = A.rhoN[n];
-    const typename V4<R>::T nsv = ld4(A.nst, n);
+    const typename V4<R>::T nsv = ld4(A.nst, t);
+    // x + c_i is the pull source of direction opp(i); where it is solid that id is the node's
+    // own, which is the value the curvature takes for a solid neighbour.
     typename V4<R>::T nbv[18];
 #pragma unroll
-    for (int i = 0; i < 18; ++i) {
-      const bool sol = (inf >> D::opp[i]) & 1u;  // x + c_i is solid: its normal is not stored
-      nbv[i] = sol ? nsv : ld4(A.nst, nb.at(D::cx[i], D::cy[i], D::cz[i]));
-    }
+    for (int i = 0; i < 18; ++i) nbv[i] = ld4(A.nst, sid[D::opp[i]]);
     // Moments (same summation order as k_colour, so rho^m agrees bit for bit).
     R rm = 0;
 #pragma unroll
