@@ -97,7 +97,7 @@ def run_mode(core, torch, w, solid, theta, rr0, rp0, precision, steps, warmup, p
         ms, n = sim.kernel_times()
         kern = {k: v / n for k, v in ms.items()}
         sim.set_profiling(False)
-    return sim, red, dt, kern
+    return sim, red, dt, kern, mom
 
 
 def adjoint_mode(core, torch, precision):

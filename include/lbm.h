@@ -135,15 +135,19 @@ lbm_status lbm_populations(lbm_ctx* ctx, void* d_fr, void* d_fp, void* d_g);
  * cos(theta) (k = 3); zero at solid nodes. Either may be NULL. */
 lbm_status lbm_geometry(lbm_ctx* ctx, void* d_info, void* d_wet);
 
-/* Byte offsets inside a state snapshot of its three parts: the 19 colour-blind population
- * planes f^m (storage type, population-major [i*N + f]), the colour scalars as one 4-vector per
- * node (e, v_x, v_y, v_z; real type, [4*f + k]) and the 7 species planes (storage type; absent
- * without species). The per-colour populations are f^r_i = a f^m_i + (w_i/|c_i|) c_i.v and
- * f^p_i = b f^m_i - (w_i/|c_i|) c_i.v with a + b = 1; e holds the smaller of a and b at full
- * precision: e = -b when the sign bit of e is set (e = -0: pure reactant colour), else e = a. The state holds fluid nodes only: f is the fluid id, the rank of the node
- * among the fluid nodes in node order (0 .. nfluid-1); entries f >= nfluid are unused. In the *_DEV storages a
- * population f is stored as (f - w_i) * 2^k (k = fp16_scale_log2 for FP16, 0 for BF16). */
-lbm_status lbm_state_layout(const lbm_params* params, size_t* f_off, size_t* a_off, size_t* g_off);
+/* Byte offsets inside a state snapshot of its three parts, and the plane stride P (elements;
+ * P >= N, padded so that planes are an odd multiple of 256 bytes apart): the 19 colour-blind
+ * population planes f^m (storage type, population-major [i*P + f]), the colour scalars as one
+ * 4-vector per node (e, v_x, v_y, v_z; real type, [4*f + k]) and the 7 species planes (storage
+ * type, [i*P + f]; absent without species). The per-colour populations are
+ * f^r_i = a f^m_i + (w_i/|c_i|) c_i.v and f^p_i = b f^m_i - (w_i/|c_i|) c_i.v with a + b = 1;
+ * e holds the smaller of a and b at full precision: e = -b when the sign bit of e is set
+ * (e = -0: pure reactant colour), else e = a. The state holds fluid nodes only: f is the fluid
+ * id, the rank of the node among the fluid nodes in node order (0 .. nfluid-1); entries
+ * f >= nfluid are unused. In the *_DEV storages a population f is stored as (f - w_i) * 2^k
+ * (k = fp16_scale_log2 for FP16, 0 for BF16). Any output pointer may be NULL. */
+lbm_status lbm_state_layout(const lbm_params* params, size_t* f_off, size_t* a_off, size_t* g_off,
+                            size_t* plane_stride);
 
 /* Copies the current state (lbm_state_bytes) to / from caller device memory, stream-ordered.
  * Together with lbm_steps_done this is a bitwise-exact checkpoint. */
@@ -161,7 +165,8 @@ lbm_status lbm_kernel_times(lbm_ctx* ctx, double* kernel_ms, int64_t* steps);
 /* Discrete adjoint of the step, for gradients of the gas production L = m^p(T) - m^p(0)
  * (eqs. product_mass, production_rate) with respect to the per-node contact angle theta(x)
  * (eq. realigned_normal_vectors) and the reaction rate xi (eq. reactive_boundary_condition_*).
- * An adjoint state holds 30 planes of N reals (context's real type), in the order of the state:
+ * An adjoint state holds 30 planes of reals (context's real type) P elements apart (the plane
+ * stride of lbm_state_layout), in the order of the state:
  * 19 colour-blind populations, the colour fraction a (dL/da; e moves with a, de/da = 1 on
  * either side of its sign), the three components of the recolouring vector v, 7 species
  * populations, each plane indexed by fluid id like the state (entries

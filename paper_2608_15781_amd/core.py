@@ -68,7 +68,7 @@ def lib():
         L.lbm_geometry.argtypes = [vp, vp, vp]
         L.lbm_get_state.argtypes = [vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, i64]
-        L.lbm_state_layout.argtypes = [P(Params), P(sz), P(sz), P(sz)]
+        L.lbm_state_layout.argtypes = [P(Params), P(sz), P(sz), P(sz), P(sz)]
         L.lbm_adjoint_bytes.argtypes = [P(Params), P(sz), P(sz)]
         L.lbm_adjoint_seed.argtypes = [vp, vp, vp]
         L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -233,11 +233,12 @@ class Lbm:
 
     # ---- state layout and adjoint -------------------------------------------------------------
     def state_layout(self):
-        """Byte offsets of the population, colour-scalar and species parts of a state snapshot."""
-        f, a, g = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        """Byte offsets of the population, colour-scalar and species parts of a state snapshot, and
+        the plane stride (elements between consecutive planes)."""
+        f, a, g, ps = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
         self._check(lib().lbm_state_layout(ctypes.byref(self.params), ctypes.byref(f), ctypes.byref(a),
-                                           ctypes.byref(g)), None)
-        return f.value, a.value, g.value
+                                           ctypes.byref(g), ctypes.byref(ps)), None)
+        return f.value, a.value, g.value, ps.value
 
     def state_parts(self, buf):
         """Views (19, F), (4, F), (7, F) of a state snapshot (FP32/FP64 storage only), F = number of
@@ -248,12 +249,11 @@ class Lbm:
             raise ValueError("state_parts needs FP32 or FP64 storage")
         dt = self.real
         es = 8 if self.precision == 0 else 4
-        f_off, a_off, g_off = self.state_layout()
-        N = self.N
+        f_off, a_off, g_off, ps = self.state_layout()
         F = self.nfluid
-        f = buf[f_off:f_off + 19 * N * es].view(dt).view(19, N)[:, :F]
-        a = buf[a_off:a_off + 4 * N * es].view(dt).view(N, 4)[:F].t()
-        g = buf[g_off:g_off + 7 * N * es].view(dt).view(7, N)[:, :F] if self.params.species else None
+        f = buf[f_off:f_off + 19 * ps * es].view(dt).view(19, ps)[:, :F]
+        a = buf[a_off:a_off + 4 * ps * es].view(dt).view(ps, 4)[:F].t()
+        g = buf[g_off:g_off + 7 * ps * es].view(dt).view(7, ps)[:, :F] if self.params.species else None
         return f, a, g
 
     def adjoint_bytes(self):
@@ -262,9 +262,9 @@ class Lbm:
         return ab.value, sb.value
 
     def new_adjoint(self):
-        """A zeroed adjoint state: (30, N) tensor of the context's real type; column f < nfluid is the
-        fluid node of rank f."""
-        return self.torch.zeros(30, self.N, dtype=self.real, device=self.device)
+        """A zeroed adjoint state: (30, P) tensor of the context's real type, P the plane stride;
+        column f < nfluid is the fluid node of rank f."""
+        return self.torch.zeros(30, self.state_layout()[3], dtype=self.real, device=self.device)
 
     def new_scratch(self):
         return self.torch.empty(self.adjoint_bytes()[1] + 256, dtype=self.torch.uint8, device=self.device)
@@ -274,8 +274,22 @@ class Lbm:
         p = t.data_ptr()
         return p + ((-p) % 256)
 
+    def _need(self, t, nbytes, what):
+        """The library reads and writes these buffers through raw device pointers: check them here."""
+        if not t.is_contiguous() or t.device != self.device or t.numel() * t.element_size() < nbytes:
+            raise ValueError("%s must be a contiguous tensor of at least %d bytes on %s" % (what, nbytes, self.device))
+
+    def _check_adjoint_args(self, state, *adj):
+        ab = self.adjoint_bytes()[0]
+        self._need(state, self.state_bytes, "state")
+        for a in adj:
+            if a.dtype != self.real:
+                raise ValueError("adjoint states are %s" % self.real)
+            self._need(a, ab, "adjoint state")
+
     def adjoint_seed(self, state, adj):
         """adj <- dL/dS_T of L = m^p(T) at the state snapshot `state`."""
+        self._check_adjoint_args(state, adj)
         self._check(lib().lbm_adjoint_seed(self._h, state.data_ptr(), adj.data_ptr()), self._h)
 
     def adjoint_step(self, state, adj_in, adj_out, scratch, grad_theta, grad_xi):
@@ -283,6 +297,10 @@ class Lbm:
         grad_xi (1 double) on the device."""
         if grad_theta.dtype != self.torch.float64 or grad_xi.dtype != self.torch.float64:
             raise ValueError("gradients accumulate in float64")
+        self._check_adjoint_args(state, adj_in, adj_out)
+        self._need(grad_theta, 8 * self.N, "grad_theta")
+        self._need(grad_xi, 8, "grad_xi")
+        self._need(scratch, self.adjoint_bytes()[1] + 255, "scratch")
         self._check(lib().lbm_adjoint_step(self._h, state.data_ptr(), adj_in.data_ptr(), adj_out.data_ptr(),
                                            ctypes.c_void_p(self._aligned(scratch)), grad_theta.data_ptr(),
                                            grad_xi.data_ptr()), self._h)

@@ -90,10 +90,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(StepArgs<P> A, typename Pre
   R s = 0;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    s += Prec<P>::ld(A.fin[size_t(i) * N + t], R(D::w(i)), A.inv_scale);
-    lout[size_t(i) * N + t] = b;
+    s += Prec<P>::ld(A.fin[size_t(i) * A.ps + t], R(D::w(i)), A.inv_scale);
+    lout[size_t(i) * A.ps + t] = b;
   }
-  lout[size_t(kAdjA) * N + t] = -s;
+  lout[size_t(kAdjA) * A.ps + t] = -s;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
       const bool bb = (i < 18) && ((inf >> i) & 1u);
       const int src = (i < 18) ? sid[i] : t;
       const int q = bb ? D::opp[i] : i;
-      f[i] = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
+      f[i] = Prec<P>::ld(A.fin[size_t(q) * A.ps + src], R(D::w(i)), A.inv_scale);
     }
     R rm = 0;
 #pragma unroll
@@ -176,14 +176,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
         if (i == 1 && outlet) {
-          g[i] = Prec<P>::ld(A.gin[N + t], R(D3Q7::w(1)), A.inv_gscale);
+          g[i] = Prec<P>::ld(A.gin[A.ps + t], R(D3Q7::w(1)), A.inv_gscale);
         } else {
           const bool bb = (inf >> i) & 1u;
           const int q = bb ? D3Q7::opp[i] : i;
-          g[i] = Prec<P>::ld(A.gin[size_t(q) * N + sid[i]], R(D3Q7::w(i)), A.inv_gscale);
+          g[i] = Prec<P>::ld(A.gin[size_t(q) * A.ps + sid[i]], R(D3Q7::w(i)), A.inv_gscale);
         }
       }
-      g[6] = Prec<P>::ld(A.gin[6 * N + t], R(D3Q7::w(6)), A.inv_gscale);
+      g[6] = Prec<P>::ld(A.gin[6 * A.ps + t], R(D3Q7::w(6)), A.inv_gscale);
       C = 0;
 #pragma unroll
       for (int i = 0; i < 7; ++i) C += g[i];
@@ -215,9 +215,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     // ---------------- reverse ----------------
     R lf[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) lf[i] = J.lin[size_t(i) * N + t];
-    const R la = J.lin[size_t(kAdjA) * N + t];
-    const R lv[3] = {J.lin[size_t(kAdjV) * N + t], J.lin[size_t(kAdjV + 1) * N + t], J.lin[size_t(kAdjV + 2) * N + t]};
+    for (int i = 0; i < 19; ++i) lf[i] = J.lin[size_t(i) * A.ps + t];
+    const R la = J.lin[size_t(kAdjA) * A.ps + t];
+    const R lv[3] = {J.lin[size_t(kAdjV) * A.ps + t], J.lin[size_t(kAdjV + 1) * A.ps + t], J.lin[size_t(kAdjV + 2) * A.ps + t]};
     R l_C = 0, l_delta = 0, l_up[3] = {0, 0, 0};
     R l_g[7] = {0, 0, 0, 0, 0, 0, 0};
     if (A.species) {
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
         const R geq = wc * C * (R(1) + R(4) * cu);
         const R gi = inlet ? geq : g[i];
         const R pre = gi + (geq - gi) * A.inv_tau_c;
-        const R lgo = J.lin[size_t(kAdjG + i) * N + t];
+        const R lgo = J.lin[size_t(kAdjG + i) * A.ps + t];
         const R l_pre = lgo * sink;
         l_sink += lgo * pre;
         R l_geq = l_pre * A.inv_tau_c;
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
       const bool bb = (i < 18) && ((inf >> i) & 1u);
       const int src = (i < 18) ? sid[i] : t;
       const int q = bb ? D::opp[i] : i;
-      J.lout[size_t(q) * N + src] = v;
+      J.lout[size_t(q) * A.ps + src] = v;
     }
     if (A.species) {
 #pragma unroll
@@ -408,10 +408,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
         } else {
           const bool bb = (inf >> i) & 1u;
           const int q = bb ? D3Q7::opp[i] : i;
-          J.lout[size_t(kAdjG + q) * N + sid[i]] = l_g[i];
+          J.lout[size_t(kAdjG + q) * A.ps + sid[i]] = l_g[i];
         }
       }
-      J.lout[size_t(kAdjG + 6) * N + t] = l_g[6];
+      J.lout[size_t(kAdjG + 6) * A.ps + t] = l_g[6];
     }
     J.lrn[n] = l_rn;
     J.lnc[n] = l_n[0];
@@ -591,19 +591,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_final(StepArgs<P> A, AdjArgs<typ
     const bool self = (q == 18) || ((inf >> D::opp[q]) & 1u);  // y + c_q solid: bounce-back reader
     const int rd = self ? n : nb.at(D::cx[q], D::cy[q], D::cz[q]);
     const R lr = J.lrr[rd], lm = J.lrm[rd];
-    const R fq = Prec<P>::ld(A.fin[size_t(q) * N + t], R(D::w(q)), A.inv_scale);
-    J.lout[size_t(q) * N + t] += lr * a + lm;
+    const R fq = Prec<P>::ld(A.fin[size_t(q) * A.ps + t], R(D::w(q)), A.inv_scale);
+    J.lout[size_t(q) * A.ps + t] += lr * a + lm;
     la += lr * fq;
     const R wl = R(D::w_over_len(q)) * lr;
     lv[0] += wl * R(D::cx[q]);
     lv[1] += wl * R(D::cy[q]);
     lv[2] += wl * R(D::cz[q]);
   }
-  J.lout[size_t(kAdjA) * N + t] = la;
-  J.lout[size_t(kAdjV) * N + t] = lv[0];
-  J.lout[size_t(kAdjV + 1) * N + t] = lv[1];
-  J.lout[size_t(kAdjV + 2) * N + t] = lv[2];
-  if (A.species && (inf & kOutlet)) J.lout[size_t(kAdjG + 1) * N + t] += J.lgo[n];
+  J.lout[size_t(kAdjA) * A.ps + t] = la;
+  J.lout[size_t(kAdjV) * A.ps + t] = lv[0];
+  J.lout[size_t(kAdjV + 1) * A.ps + t] = lv[1];
+  J.lout[size_t(kAdjV + 2) * A.ps + t] = lv[2];
+  if (A.species && (inf & kOutlet)) J.lout[size_t(kAdjG + 1) * A.ps + t] += J.lgo[n];
 }
 
 __global__ void k_add_scalar(const double* src, double* dst) {

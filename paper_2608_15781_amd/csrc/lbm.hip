@@ -31,17 +31,31 @@ size_t real_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 struct Layout {
   size_t info, wet, rhoN, nst, state[2], partials, ring, lists[2], linfo[2], fid, counts, total;
   size_t f_off, a_off, g_off, state_bytes;  // within one state buffer
+  size_t ps;  // elements between consecutive state (and adjoint) planes
   int nblocks;  // one thread per node, rounded up to a multiple of kXcd workgroups
 };
+
+// Plane stride: at least N elements and an odd multiple of 256 bytes of storage, so that the
+// same entry of different planes does not fall on one memory channel (N = 2^k would put every
+// plane 2^k elements apart).
+size_t plane_stride(const lbm_params& p) {
+  const size_t N = size_t(p.nx) * p.ny * p.nz;
+  const size_t unit = 256 / store_bytes(p.precision);
+  size_t m = (N + unit - 1) / unit;
+  if (m % 2 == 0) ++m;
+  return m * unit;
+}
 
 Layout make_layout(const lbm_params& p) {
   Layout L{};
   const size_t N = size_t(p.nx) * p.ny * p.nz;
   const size_t s = store_bytes(p.precision), r = real_bytes(p.precision);
+  const size_t ps = plane_stride(p);
+  L.ps = ps;
   L.f_off = 0;
-  L.a_off = align_up(19 * s * N);
-  L.g_off = align_up(L.a_off + 4 * r * N);
-  L.state_bytes = align_up(L.g_off + (p.species ? 7 * s * N : 0));
+  L.a_off = align_up(19 * s * ps);
+  L.g_off = align_up(L.a_off + 4 * r * ps);
+  L.state_bytes = align_up(L.g_off + (p.species ? 7 * s * ps : 0));
   int nb = int((N + kBlock - 1) / kBlock);
   nb = (nb + kXcd - 1) / kXcd * kXcd;
   L.nblocks = nb;
@@ -73,7 +87,7 @@ AdjLayout make_adj_layout(const lbm_params& p) {
   AdjLayout A{};
   const size_t N = size_t(p.nx) * p.ny * p.nz;
   const size_t r = real_bytes(p.precision);
-  A.adj_bytes = align_up(size_t(kAdjPlanes) * r * N);
+  A.adj_bytes = align_up(size_t(kAdjPlanes) * r * plane_stride(p));
   size_t o = 0;
   A.lrn = o; o = align_up(o + r * N);
   A.lnc = o; o = align_up(o + 3 * r * N);
@@ -251,11 +265,11 @@ __global__ void k_init_state(StepArgs<P> A, const double* rr0, const double* rp0
   const int n = A.fluid[t];
   const size_t N = A.N;
   const double rm = rr0[n] + rp0[n];
-  for (int i = 0; i < 19; ++i) A.fout[size_t(i) * N + t] = Prec<P>::st(R(D::w(i) * rm), R(D::w(i)), A.scale);
+  for (int i = 0; i < 19; ++i) A.fout[size_t(i) * A.ps + t] = Prec<P>::st(R(D::w(i) * rm), R(D::w(i)), A.scale);
   st4(A.aout, t, R(pack_frac(rr0[n] / rm, rp0[n] / rm)), R(0), R(0), R(0));
   if (A.species) {
     const double c = c0 ? c0[n] : 1.0;
-    for (int i = 0; i < 7; ++i) A.gout[size_t(i) * N + t] = Prec<P>::st(R(D3Q7::w(i) * c), R(D3Q7::w(i)), A.gscale);
+    for (int i = 0; i < 7; ++i) A.gout[size_t(i) * A.ps + t] = Prec<P>::st(R(D3Q7::w(i) * c), R(D3Q7::w(i)), A.gscale);
   }
 }
 
@@ -340,6 +354,7 @@ StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
   const lbm_params& p = c->p;
   const Layout& L = c->L;
   A.nx = p.nx; A.ny = p.ny; A.nz = p.nz; A.N = c->N;
+  A.ps = L.ps;
   A.geo.nx = p.nx; A.geo.ny = p.ny; A.geo.nz = p.nz;
   A.geo.fx = make_fastdiv(uint32_t(p.nx));
   A.geo.fy = make_fastdiv(uint32_t(p.ny));
@@ -767,10 +782,12 @@ lbm_status lbm_geometry(lbm_ctx* c, void* d_info, void* d_wet) {
   return LBM_OK;
 }
 
-lbm_status lbm_state_layout(const lbm_params* params, size_t* f_off, size_t* a_off, size_t* g_off) {
+lbm_status lbm_state_layout(const lbm_params* params, size_t* f_off, size_t* a_off, size_t* g_off,
+                            size_t* plane_stride_out) {
   lbm_status s = check_params(params, g_err, sizeof(g_err));
   if (s != LBM_OK) return s;
   const Layout L = make_layout(*params);
+  if (plane_stride_out) *plane_stride_out = L.ps;
   if (f_off) *f_off = L.f_off;
   if (a_off) *a_off = L.a_off;
   if (g_off) *g_off = L.g_off;

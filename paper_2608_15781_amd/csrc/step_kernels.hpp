@@ -24,7 +24,8 @@
 // ((1 + rho^N)/2, (1 - rho^N)/2) is stored at full relative precision, the sign bit telling
 // which one it is. Colour densities and gradients of rho^N are formed from those directly.
 //
-// Layout: structure of arrays, one plane per population, fluid ids in node order (x fastest);
+// Layout: structure of arrays, one plane per population (planes a padded stride ps >= N apart),
+// fluid ids in node order (x fastest);
 // the colour scalars (a, v) as one 4-vector per fluid node. Two state buffers are used
 // alternately (pull from one, write the other), so no kernel reads what another thread of the
 // same launch writes.
@@ -160,6 +161,7 @@ struct StepArgs {
   using S = typename Prec<P>::S;
   using R = typename Prec<P>::R;
   int nx, ny, nz, N;
+  size_t ps;              // plane stride of the state and adjoint planes (>= N elements)
   Geom geo;
   const int* fluid;       // dense indices of the fluid nodes, in increasing order
   const uint32_t* finfo;  // their info words
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
     const int src = bb ? t : A.fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
     const int q = bb ? D::opp[i] : i;
     const R sgn = bb ? R(-1) : R(1);  // c_q = sgn * c_i
-    const R fm = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
+    const R fm = Prec<P>::ld(A.fin[size_t(q) * A.ps + src], R(D::w(i)), A.inv_scale);
     const typename V4<R>::T av = ld4(A.ain, src);
     // all three products, zeros included, so that the 4-vector is fetched by one wide load
     const R cv = R(D::cx[i]) * av.y + R(D::cy[i]) * av.z + R(D::cz[i]) * av.w;
@@ -465,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
       const bool bb = (i < 18) && ((inf >> i) & 1u);
       const int src = (i < 18) ? sid[i] : t;
       const int q = bb ? D::opp[i] : i;
-      f[i] = Prec<P>::ld(A.fin[size_t(q) * N + src], R(D::w(i)), A.inv_scale);
+      f[i] = Prec<P>::ld(A.fin[size_t(q) * A.ps + src], R(D::w(i)), A.inv_scale);
     }
     R g[7] = {0, 0, 0, 0, 0, 0, 0};
     if (A.species) {
@@ -476,9 +478,9 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
         const bool bb = !own && ((inf >> i) & 1u);
         const int src = own ? t : sid[i];
         const int q = own ? 1 : (bb ? D3Q7::opp[i] : i);
-        g[i] = Prec<P>::ld(A.gin[size_t(q) * N + src], R(D3Q7::w(i)), A.inv_gscale);
+        g[i] = Prec<P>::ld(A.gin[size_t(q) * A.ps + src], R(D3Q7::w(i)), A.inv_gscale);
       }
-      g[6] = Prec<P>::ld(A.gin[6 * N + t], R(D3Q7::w(6)), A.inv_gscale);
+      g[6] = Prec<P>::ld(A.gin[6 * A.ps + t], R(D3Q7::w(6)), A.inv_gscale);
     }
     const R rn = A.rhoN[n];
     const typename V4<R>::T nsv = ld4(A.nst, t);
@@ -608,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
       const R vc = keep * A.beta * rr * rp * irm;
       const R v0 = has_n ? vc * n0 : R(0), v1 = has_n ? vc * n1 : R(0), v2 = has_n ? vc * n2 : R(0);
 #pragma unroll
-      for (int i = 0; i < 19; ++i) A.fout[size_t(i) * N + t] = Prec<P>::st(fs[i], R(D::w(i)), A.scale);
+      for (int i = 0; i < 19; ++i) A.fout[size_t(i) * A.ps + t] = Prec<P>::st(fs[i], R(D::w(i)), A.scale);
       st4(A.aout, t, aout, v0, v1, v2);
       bool ok = finite(fsum) && finite(aout) && finite(v0 + v1 + v2) && finite(rr) && finite(rp);
       if (A.species) {
@@ -624,7 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
           const R gi = inlet ? geq : g[i];
           const R go = (gi + (geq - gi) * A.inv_tau_c) * sink;
           gs += go;
-          A.gout[size_t(i) * N + t] = Prec<P>::st(go, R(D3Q7::w(i)), A.gscale);
+          A.gout[size_t(i) * A.ps + t] = Prec<P>::st(go, R(D3Q7::w(i)), A.gscale);
         }
         ok = ok && finite(gs);
       }
@@ -659,7 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(StepArgs<P> A, typename Prec<
   unpack_frac(av.x, a, b);
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    const R fm = fluid ? Prec<P>::ld(A.fin[size_t(i) * N + fi], R(D::w(i)), A.inv_scale) : R(0);
+    const R fm = fluid ? Prec<P>::ld(A.fin[size_t(i) * A.ps + fi], R(D::w(i)), A.inv_scale) : R(0);
     const R kv = R(D::w_over_len(i)) * (R(D::cx[i]) * v0 + R(D::cy[i]) * v1 + R(D::cz[i]) * v2);
     fr[size_t(i) * N + n] = fluid ? a * fm + kv : R(0);
     fp[size_t(i) * N + n] = fluid ? b * fm - kv : R(0);
@@ -667,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(StepArgs<P> A, typename Prec<
   if (go) {
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-      go[size_t(i) * N + n] = (fluid && A.species) ? Prec<P>::ld(A.gin[size_t(i) * N + fi], R(D3Q7::w(i)), A.inv_gscale) : R(0);
+      go[size_t(i) * N + n] = (fluid && A.species) ? Prec<P>::ld(A.gin[size_t(i) * A.ps + fi], R(D3Q7::w(i)), A.inv_gscale) : R(0);
   }
 }
 
