@@ -178,3 +178,91 @@ def test_contact_angle_gradient_finite_differences_on_wall_nodes(core):
         fd = (Lp - Lm) / (2 * eps)
         print("node %d adjoint %.10e fd %.10e" % (k, g[k], fd), flush=True)
         assert abs(g[k] - fd) < 1e-5 * abs(g[order[0]]) + 1e-6 * abs(fd), (k, g[k], fd)
+
+
+def _adjoint96():
+    from paper_2608_15781_amd import inputs
+
+    w, solid, theta, rr0, rp0 = inputs.workload_inputs("adjoint96")
+    kw = dict(tau=w["tau"], sigma=w["sigma"], beta=w["beta"], accel=[(w["accel"], 0, 0)] * 2, species=w["species"],
+              x_open=w["x_open"])
+    return w, solid, theta, rr0, rp0, kw
+
+
+def test_adjoint96_gradient_against_finite_differences(core):
+    """The 96^3 adjoint workload at full size (200 steps, checkpoint every 20), FP64: dL/dtheta on
+    32 wetting nodes (the 16 largest |dL/dtheta| and 16 drawn at random) against central
+    differences, and dL/dxi against a central difference in xi.
+
+    L is strongly nonlinear in theta at the nodes of largest gradient: there the central quotient
+    with eps = 1e-4 rad is still far from its limit (13.6 at eps -> 0, 18.2 at 1e-4, 11.6 at 1e-3
+    on the largest node), so the comparison uses eps = 1e-7, where the quotient has converged to
+    about 1e-7 relative; the quotient at eps = 1e-4 is printed beside it."""
+    from paper_2608_15781_amd import autograd as ag
+
+    w, solid, theta, rr0, rp0, kw = _adjoint96()
+    T, ck = w["steps"], w["checkpoint"]
+
+    def make(th, xi):
+        return core.Lbm(w["shape"], solid=solid, theta=th, rho_r0=rr0, rho_p0=rp0, xi=xi, precision="fp64",
+                        tau_species=w["tau_c"], c_inlet=w["c_in"], **kw)
+
+    def central(k, eps):
+        tp = theta.ravel().copy()
+        tm = theta.ravel().copy()
+        tp[k] += eps
+        tm[k] -= eps
+        Lp = float(make(tp.reshape(theta.shape), w["xi"]).step(T)[:, 2].sum())
+        Lm = float(make(tm.reshape(theta.shape), w["xi"]).step(T)[:, 2].sum())
+        return (Lp - Lm) / (2 * eps)
+
+    sim = make(theta, w["xi"])
+    L0, cps, final = ag.forward_states(sim, T, ck)
+    gth, gxi, _ = ag.adjoint_gradients(sim, T, ck, cps, final)
+    g = gth.cpu().numpy()
+    del sim, cps, final
+    order = np.argsort(-np.abs(g))
+    rng = np.random.default_rng(11)
+    wet = np.setdiff1d(np.flatnonzero(g != 0), order[:16])
+    picks = list(order[:16]) + list(rng.choice(wet, 16, replace=False))
+    gmax = abs(g[order[0]])
+    worst = 0.0
+    for k in picks:
+        fd7 = central(k, 1e-7)
+        fd4 = central(k, 1e-4)
+        worst = max(worst, abs(g[k] - fd7) / gmax)
+        print("node %7d adjoint %+.8e fd(1e-7) %+.8e fd(1e-4) %+.8e" % (k, g[k], fd7, fd4), flush=True)
+        assert abs(g[k] - fd7) < 1e-5 * gmax + 1e-5 * abs(fd7), (k, g[k], fd7)
+    hx = 1e-9  # L is curved in xi too: at hx = 1e-7 the central quotient is still 5e-6 off
+    fdx = (float(make(theta, w["xi"] + hx).step(T)[:, 2].sum()) -
+           float(make(theta, w["xi"] - hx).step(T)[:, 2].sum())) / (2 * hx)
+    print("xi: adjoint %.10e fd %.10e; worst theta error / max|g| %.2e" % (float(gxi), fdx, worst), flush=True)
+    assert abs(float(gxi) - fdx) < 1e-6 * abs(fdx)
+
+
+def test_adjoint96_crop_gradient_against_oracle_duals(core, oracle_mod):
+    """The [0, 24)^3 crop of the 96^3 adjoint workload (periodic as a domain of its own), 200 FP64
+    steps with checkpoints every 20: directional derivatives of L along two random theta
+    perturbations and along xi, against the oracle's forward-mode dual numbers."""
+    from paper_2608_15781_amd import autograd as ag
+    from paper_2608_15781_amd import inputs
+
+    w, solid, theta, rr0, rp0, kw = _adjoint96()
+    n = 24
+    solid, theta, rr0, rp0 = (inputs.crop(a, n) for a in (solid, theta, rr0, rp0))
+    T, ck, xi = w["steps"], w["checkpoint"], w["xi"]
+    rng = np.random.default_rng(5)
+    d1 = rng.normal(size=solid.shape) * (1 - solid)
+    d2 = rng.normal(size=solid.shape) * (1 - solid)
+    L, dL = oracle_mod.grad((n, n, n), solid, theta, xi, T, dtheta=[d1.ravel(), d2.ravel(), np.zeros(n ** 3)],
+                            dxi=[0.0, 0.0, 1.0], rho_r0=rr0, tau_c=w["tau_c"], c_in=w["c_in"], **kw)
+    sim = core.Lbm((n, n, n), solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, xi=xi, precision="fp64",
+                   tau_species=w["tau_c"], c_inlet=w["c_in"], **kw)
+    Lg, cps, final = ag.forward_states(sim, T, ck)
+    gth, gxi, _ = ag.adjoint_gradients(sim, T, ck, cps, final)
+    g = gth.cpu().numpy()
+    ad = [float(g @ d1.ravel()), float(g @ d2.ravel()), float(gxi)]
+    print("crop24: L gpu %.12e oracle %.12e; dL adjoint %s oracle %s" % (Lg, L, ad, list(dL)), flush=True)
+    assert abs(Lg - L) < 1e-10 * abs(L)
+    for a, b in zip(ad, dL):
+        assert abs(a - b) < 1e-8 * abs(b) + 1e-14, (a, b)
