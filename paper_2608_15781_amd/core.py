@@ -160,6 +160,7 @@ class Lbm:
                             _p(rp), _p(c0a), ctypes.c_void_p(self._ws_ptr), self.workspace_bytes,
                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         self._check(st, None)
+        self._lib = L
         self._h = h
 
     def _check(self, status, h):
@@ -170,7 +171,8 @@ class Lbm:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().lbm_free(h)
+            # the library handle is held by the instance: module globals may be gone at exit
+            self._lib.lbm_free(h)
             self._h = None
 
     close = __del__

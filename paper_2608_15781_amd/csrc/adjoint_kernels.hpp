@@ -7,7 +7,9 @@
 // extrapolation and normal kernels; the reverse pass then runs
 //   k_adj_collide   reverse of the collide kernel at each fluid node; the pull transposes to a
 //                   scatter that is a bijection on (node, direction), so every adjoint population
-//                   is written exactly once, without atomics
+//                   is written exactly once, without atomics (and the output needs no clearing;
+//                   the one entry without a reader, S_1 at an inlet facing an outflow node, is
+//                   zeroed by k_adj_final)
 //   k_adj_normal    curvature transpose (gather of the neighbours' dH/dn*), then the normal and
 //                   Akai realignment reversed to d/dG; accumulates dL/dtheta
 //   k_adj_grad      transpose of the isotropic gradient stencil (gather), fluid and solid nodes
@@ -41,6 +43,9 @@ struct AdjArgs {
   const R* rmv;      // rho^m of level t (forward recompute)
   double* gtheta;    // dL/dtheta per node (accumulated)
   double* partials;  // dL/dxi per workgroup (5 planes of workgroup sums, slot 0 used)
+  int nparts;        // number of workgroups of k_adj_collide
+  double* sum;       // 5 doubles: the reduced partials
+  double* gxi;       // dL/dxi (accumulated)
 };
 
 // Forward-mode dual with one derivative, used to take the vector-Jacobian product of the
@@ -431,6 +436,11 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
+  // Workgroup 0 first finishes the xi sum of k_adj_collide and adds it to dL/dxi.
+  if (blockIdx.x == 0) {
+    reduce_partials(J.partials, J.nparts, J.sum);
+    if (threadIdx.x == 0) *J.gxi += J.sum[0];
+  }
   const int t = logical_block() * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
@@ -604,10 +614,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_final(StepArgs<P> A, AdjArgs<typ
   J.lout[size_t(kAdjV + 1) * A.ps + t] = lv[1];
   J.lout[size_t(kAdjV + 2) * A.ps + t] = lv[2];
   if (A.species && (inf & kOutlet)) J.lout[size_t(kAdjG + 1) * A.ps + t] += J.lgo[n];
+  // Species populations without a reader, which the scatter of k_adj_collide left untouched:
+  // their adjoint is zero. An outflow node takes its own S_1 instead of the one from its periodic
+  // +x image, so S_1 of an inlet node whose -x image is an outflow node is unread, and S_0 of an
+  // outflow node whose +x image is solid is unread (bounce-back would have read it).
+  if (A.species && (inf & kInlet) && !(inf & 1u)) J.lout[size_t(kAdjG + 1) * A.ps + t] = R(0);
+  if (A.species && (inf & kOutlet) && (inf & 2u)) J.lout[size_t(kAdjG + 0) * A.ps + t] = R(0);
 }
 
-__global__ void k_add_scalar(const double* src, double* dst) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst += *src;
-}
 
 }  // namespace lbm

@@ -557,18 +557,17 @@ lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* lin, void*
   J.rmv = A.rm_out;
   J.gtheta = gth;
   J.partials = reinterpret_cast<double*>(sc + AL.partials);
-  double* sum = reinterpret_cast<double*>(sc + AL.sum);
+  J.nparts = c->nb_fluid;
+  J.sum = reinterpret_cast<double*>(sc + AL.sum);
+  J.gxi = gxi;
   const dim3 gf(c->nb_fluid), ge(c->nb_ext), block(kBlock);
   // Forward fields of level t.
   if (c->nb_fluid) hipLaunchKernelGGL(k_colour<P>, gf, block, 0, c->stream, A);
   if (c->nb_ext) hipLaunchKernelGGL(k_extrap<P>, ge, block, 0, c->stream, A);
   if (c->nb_fluid) hipLaunchKernelGGL(k_normal<P>, gf, block, 0, c->stream, A);
-  // Reverse pass.
-  HIP_TRY(c, hipMemsetAsync(lout, 0, AL.adj_bytes, c->stream));
+  // Reverse pass. Every entry of lout a fluid node owns is written (see k_adj_collide).
   if (c->nb_fluid) {
     hipLaunchKernelGGL(k_adj_collide<P>, gf, block, 0, c->stream, A, J);
-    hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlock), 0, c->stream, J.partials, c->nb_fluid, sum);
-    hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, c->stream, sum, gxi);
     hipLaunchKernelGGL(k_adj_normal<P>, gf, block, 0, c->stream, A, J);
     hipLaunchKernelGGL((k_adj_grad<P, false>), gf, block, 0, c->stream, A, J);
     if (c->nb_ext) hipLaunchKernelGGL((k_adj_grad<P, true>), ge, block, 0, c->stream, A, J);

@@ -25,6 +25,26 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
 
+def run_adjoint(args):
+    """Forward with checkpoints and the checkpointed backward of the 96^3 adjoint workload."""
+    sys.path.insert(0, ROOT)
+    import torch
+
+    from paper_2608_15781_amd import autograd as ag
+    from paper_2608_15781_amd import core, inputs
+
+    w, solid, theta, rr0, rp0 = inputs.workload_inputs("adjoint96", device="cuda:0")
+    kw = dict(tau=w["tau"], sigma=w["sigma"], beta=w["beta"], xi=w["xi"], accel=[(w["accel"], 0, 0)] * 2,
+              species=w["species"], x_open=w["x_open"], tau_species=w["tau_c"], c_inlet=w["c_in"])
+    sim = core.Lbm(w["shape"], solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision=args.precision, **kw)
+    steps = args.steps
+    L, cps, final = ag.forward_states(sim, steps, w["checkpoint"])
+    gth, gxi, _ = ag.adjoint_gradients(sim, steps, w["checkpoint"], cps, final)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(workload="adjoint96", precision=args.precision, steps=steps,
+                          fluid_nodes=int((solid == 0).sum()), L=L, dxi=float(gxi))), flush=True)
+
+
 def run(args):
     sys.path.insert(0, ROOT)
     import torch
@@ -177,6 +197,8 @@ def main():
     elif args.cmd == "report":
         args.trace = args.out
         report(args)
+    elif args.cmd == "adjoint":
+        run_adjoint(args)
     else:
         run(args)
 
