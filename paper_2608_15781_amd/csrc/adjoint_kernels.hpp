@@ -48,35 +48,114 @@ struct AdjArgs {
   double* gxi;       // dL/dxi (accumulated)
 };
 
-// Forward-mode dual with one derivative, used to take the vector-Jacobian product of the
-// closed-form back transform eight times (one seed per input).
-template <class R>
-struct Dl {
-  R v, d;
-  __device__ Dl() {}
-  __device__ Dl(double x) : v(R(x)), d(R(0)) {}
-  __device__ Dl(R x, R dx) : v(x), d(dx) {}
-};
-template <class R> __device__ inline Dl<R> operator+(Dl<R> a, Dl<R> b) { return Dl<R>(a.v + b.v, a.d + b.d); }
-template <class R> __device__ inline Dl<R> operator-(Dl<R> a, Dl<R> b) { return Dl<R>(a.v - b.v, a.d - b.d); }
-template <class R> __device__ inline Dl<R> operator-(Dl<R> a) { return Dl<R>(-a.v, -a.d); }
-template <class R> __device__ inline Dl<R> operator*(Dl<R> a, Dl<R> b) { return Dl<R>(a.v * b.v, a.d * b.v + a.v * b.d); }
-
-// (d/d(ux,uy,uz,k5..k9)) of sum_i ld_i d_i(u, k).
+// Vector-Jacobian product of the closed-form back transform (cm_back): given ld_i, the
+// derivatives of sum_i ld_i d_i(u, k) with respect to (u_x, u_y, u_z, k5..k9), written out from
+// the same regrouped expressions (q_x = u_x^2 + s_x u_x for a move with x component s_x, and so
+// on; e_x = 2 u_x + s_x = dq_x/du_x).
 template <class R>
 __device__ inline void cm_back_vjp(const R in[8], const R ld[19], R out[8]) {
-#pragma unroll 1
-  for (int s = 0; s < 8; ++s) {
-    Dl<R> x[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = Dl<R>(in[j], j == s ? R(1) : R(0));
-    Dl<R> d[19];
-    cm_back(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], d);
-    R acc = 0;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) acc += ld[i] * d[i].d;
-    out[s] = acc;
+  const R ux = in[0], uy = in[1], uz = in[2], k5 = in[3], k6 = in[4], k7 = in[5], k8 = in[6], k9 = in[7];
+  const R x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
+  const R ax = k5 * R(1.0 / 3.0) + k6 * R(1.0 / 6.0);
+  const R ay = (k6 - k5) * R(1.0 / 6.0);
+  const R az = -(k5 * R(1.0 / 6.0) + k6 * R(1.0 / 3.0));
+  const R tx = uy * k7 + uz * k8, ty = ux * k7 + uz * k9, tz = ux * k8 + uy * k9;
+  R gux = 0, guy = 0, guz = 0, g5 = 0, g6 = 0, g7 = 0, g8 = 0, g9 = 0;
+  // moves along one axis: d = (q_a - (other squares) + 1) a_a - e_a t_a
+  {
+    const R lp = ld[0], lm = ld[1], ls = lp + lm;
+    const R ep = ux + ux + R(1), em = ux + ux - R(1);
+    const R lax = lp * (x2 + ux - y2 - z2 + R(1)) + lm * (x2 - ux - y2 - z2 + R(1));
+    const R ltx = -(lp * ep + lm * em);
+    gux += ax * (lp * ep + lm * em) - R(2) * tx * ls;
+    guy += -R(2) * uy * ax * ls + ltx * k7;
+    guz += -R(2) * uz * ax * ls + ltx * k8;
+    g7 += ltx * uy;
+    g8 += ltx * uz;
+    g5 += lax * R(1.0 / 3.0);
+    g6 += lax * R(1.0 / 6.0);
   }
+  {
+    const R lp = ld[2], lm = ld[3], ls = lp + lm;
+    const R ep = uy + uy + R(1), em = uy + uy - R(1);
+    const R lay = lp * (y2 + uy - x2 - z2 + R(1)) + lm * (y2 - uy - x2 - z2 + R(1));
+    const R lty = -(lp * ep + lm * em);
+    guy += ay * (lp * ep + lm * em) - R(2) * ty * ls;
+    gux += -R(2) * ux * ay * ls + lty * k7;
+    guz += -R(2) * uz * ay * ls + lty * k9;
+    g7 += lty * ux;
+    g9 += lty * uz;
+    g5 -= lay * R(1.0 / 6.0);
+    g6 += lay * R(1.0 / 6.0);
+  }
+  {
+    const R lp = ld[4], lm = ld[5], ls = lp + lm;
+    const R ep = uz + uz + R(1), em = uz + uz - R(1);
+    const R laz = lp * (z2 + uz - x2 - y2 + R(1)) + lm * (z2 - uz - x2 - y2 + R(1));
+    const R ltz = -(lp * ep + lm * em);
+    guz += az * (lp * ep + lm * em) - R(2) * tz * ls;
+    gux += -R(2) * ux * az * ls + ltz * k8;
+    guy += -R(2) * uy * az * ls + ltz * k9;
+    g8 += ltz * ux;
+    g9 += ltz * uy;
+    g5 -= laz * R(1.0 / 6.0);
+    g6 -= laz * R(1.0 / 3.0);
+  }
+  // diagonal moves, (d index, sign of the first axis, sign of the second axis)
+  const int xy[4][3] = {{6, 1, 1}, {7, 1, -1}, {10, -1, 1}, {11, -1, -1}};
+  const int xz[4][3] = {{8, 1, 1}, {9, 1, -1}, {12, -1, 1}, {13, -1, -1}};
+  const int yz[4][3] = {{14, 1, 1}, {15, 1, -1}, {16, -1, 1}, {17, -1, -1}};
+  const R c12 = R(1.0 / 12.0);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    // xy plane: ((2 q_y - q_x) k5 + (q_x + q_y) k6)/12 + e_x e_y k7/4
+    const R l = ld[xy[m][0]];
+    const R sx = R(xy[m][1]), sy = R(xy[m][2]);
+    const R qx = x2 + sx * ux, qy = y2 + sy * uy, ex = ux + ux + sx, ey = uy + uy + sy;
+    gux += l * ((k6 - k5) * c12 * ex + R(0.5) * ey * k7);
+    guy += l * ((k5 + k5 + k6) * c12 * ey + R(0.5) * ex * k7);
+    g5 += l * (qy + qy - qx) * c12;
+    g6 += l * (qx + qy) * c12;
+    g7 += l * R(0.25) * ex * ey;
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    // xz plane: ((2 q_z - q_x) k5 + (q_z - 2 q_x) k6)/12 + e_x e_z k8/4
+    const R l = ld[xz[m][0]];
+    const R sx = R(xz[m][1]), sz = R(xz[m][2]);
+    const R qx = x2 + sx * ux, qz = z2 + sz * uz, ex = ux + ux + sx, ez = uz + uz + sz;
+    gux += l * (-(k5 + k6 + k6) * c12 * ex + R(0.5) * ez * k8);
+    guz += l * ((k5 + k5 + k6) * c12 * ez + R(0.5) * ex * k8);
+    g5 += l * (qz + qz - qx) * c12;
+    g6 += l * (qz - qx - qx) * c12;
+    g8 += l * R(0.25) * ex * ez;
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    // yz plane: (-(q_y + q_z) k5 + (q_z - 2 q_y) k6)/12 + e_y e_z k9/4
+    const R l = ld[yz[m][0]];
+    const R sy = R(yz[m][1]), sz = R(yz[m][2]);
+    const R qy = y2 + sy * uy, qz = z2 + sz * uz, ey = uy + uy + sy, ez = uz + uz + sz;
+    guy += l * (-(k5 + k6 + k6) * c12 * ey + R(0.5) * ez * k9);
+    guz += l * ((k6 - k5) * c12 * ez + R(0.5) * ey * k9);
+    g5 -= l * (qy + qz) * c12;
+    g6 += l * (qz - qy - qy) * c12;
+    g9 += l * R(0.25) * ey * ez;
+  }
+  {
+    // rest: ((y2 + z2 - 2 x2) k5 + (2 z2 - x2 - y2) k6)/3 + 4 (ux uy k7 + ux uz k8 + uy uz k9)
+    const R l = ld[18];
+    gux += l * (-(R(4) * k5 + R(2) * k6) * ux * R(1.0 / 3.0) + R(4) * (uy * k7 + uz * k8));
+    guy += l * ((R(2) * k5 - R(2) * k6) * uy * R(1.0 / 3.0) + R(4) * (ux * k7 + uz * k9));
+    guz += l * ((R(2) * k5 + R(4) * k6) * uz * R(1.0 / 3.0) + R(4) * (ux * k8 + uy * k9));
+    g5 += l * (y2 + z2 - x2 - x2) * R(1.0 / 3.0);
+    g6 += l * (z2 + z2 - x2 - y2) * R(1.0 / 3.0);
+    g7 += l * R(4) * ux * uy;
+    g8 += l * R(4) * ux * uz;
+    g9 += l * R(4) * uy * uz;
+  }
+  out[0] = gux; out[1] = guy; out[2] = guz;
+  out[3] = g5; out[4] = g6; out[5] = g7; out[6] = g8; out[7] = g9;
 }
 
 // ---------------------------------------------------------------------------------------------
