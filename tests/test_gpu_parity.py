@@ -279,12 +279,11 @@ def test_bench_workload_full_size(core, oracle_mod):
     configuration the benchmark times, against the oracle after 1 and 3 steps.
 
     FP64 storage: every field and population within FP64_TOL (max norm).
-    FP32 storage: densities, colour function, species and populations in max norm within
-    FULL_FP32_TOL. The velocity is compared in relative L2 norm: gas films created by the wall
-    reaction lie within the 0.57-degree no-rotation cone of the wetting rule, and at the few
-    nodes whose cone test differs between FP32 and FP64 rounding the realigned normal (hence the
-    curvature force there) changes by O(1), which dominates the max norm of a velocity field
-    that is still ~1e-5 after 3 steps."""
+    FP32 storage: densities, colour function, species and populations in max norm within 1e-6
+    after 1 step and 2e-6 after 3 (FP32 rounding of values of order 1, including the trace gas
+    colour, which the minority form keeps at relative precision). The velocity is ~1e-6 here and
+    is the small difference of populations of order 0.03, so its FP32 resolution is ~1e-3
+    relative: it is compared in relative L2 norm (1e-2, 2e-2)."""
     from paper_2608_15781_amd import inputs
 
     w, solid, theta, rr0, rp0 = inputs.workload_inputs("bijel128")
@@ -299,7 +298,7 @@ def test_bench_workload_full_size(core, oracle_mod):
     red_ref = np.concatenate(red_ref)
     kw["tau_species"] = kw.pop("tau_c")
     kw["c_inlet"] = kw.pop("c_in")
-    FULL_FP32_TOL = {"rho_r": 1e-5, "rho_n": 1e-5, "c": 1e-5, "rho_p": 1e-3, "pops": 1e-4}
+    FULL_FP32_TOL = {"rho_r": 1e-6, "rho_n": 1e-6, "c": 1e-6, "rho_p": 1e-6, "pops": 1e-6}
     for precision in ("fp64", "fp32"):
         g = core.Lbm(w["shape"], solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision=precision, **kw)
         reds = []
@@ -321,9 +320,9 @@ def test_bench_workload_full_size(core, oracle_mod):
                     assert mx[k] < tol, (t, k, mx[k])
                 assert l2["u"] < 1e-2, l2["u"]
             else:
-                for k in ("rho_r", "rho_n", "c"):
-                    assert l2[k] < 1e-4, (t, k, l2[k])
-                assert l2["rho_p"] < 1e-2 and l2["u"] < 5e-2, l2
+                for k in ("rho_r", "rho_p", "rho_n", "c", "pops"):
+                    assert mx[k] < 2e-6, (t, k, mx[k])
+                assert l2["u"] < 2e-2, l2
         red = np.concatenate(reds)
         tol = FP64_TOL if precision == "fp64" else 1e-4
         for j in (0, 1, 3):
