@@ -115,6 +115,13 @@ lbm_status lbm_init(const lbm_params* params, const uint8_t* solid, const double
  * last step is kept). */
 lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps, lbm_reductions* per_step);
 
+/* The same nsteps >= 0 time steps, only enqueued on the context's stream: returns without
+ * waiting, computes no host-visible reductions and does not report non-finite values (the step
+ * kernels are the ones lbm_step launches, so the state is bitwise the same). For drivers that
+ * keep the stream busy, such as the recomputation of a checkpoint segment. Kernel timing
+ * (lbm_set_profiling) does not cover these steps. Errors: LBM_ERR_ARG, LBM_ERR_HIP. */
+lbm_status lbm_step_async(lbm_ctx* ctx, int32_t nsteps);
+
 /* Level-t fields of the current state without changing it (steps up to the forcing of the
  * next update): rho^r, rho^p, rho^N (N each), the physical velocity u + F/(2 rho^m)
  * (3N, component-major) and the species concentration C (N; 1 without species). Device

@@ -59,8 +59,8 @@ def adjoint_gradients(sim, steps, checkpoint, cps, final_state):
         sim.set_state(cps[s0], s0)
         seg = [cps[s0]]
         for _ in range(s0, s1 - 1):
-            sim.step(1, reductions=False)
-            seg.append(sim.get_state())
+            sim.advance(1)  # stream-ordered: no host round trip inside the segment
+            seg.append(sim.get_state(sync=False))
         for t in range(s1 - 1, s0 - 1, -1):
             sim.adjoint_step(seg[t - s0], lam, lam2, scratch, gth, gxi)
             lam, lam2 = lam2, lam

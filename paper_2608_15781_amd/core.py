@@ -16,7 +16,8 @@ from . import build as _build
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 LBM_OK, LBM_ERR_ARG, LBM_ERR_ALLOC, LBM_ERR_HIP, LBM_ERR_NONFINITE, LBM_ERR_STATE, LBM_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-EXPORTED = ["lbm_version", "lbm_workspace_bytes", "lbm_state_bytes", "lbm_init", "lbm_step", "lbm_moments",
+EXPORTED = ["lbm_version", "lbm_workspace_bytes", "lbm_state_bytes", "lbm_init", "lbm_step", "lbm_step_async",
+            "lbm_moments",
             "lbm_populations", "lbm_geometry", "lbm_state_layout", "lbm_get_state", "lbm_set_state",
             "lbm_set_profiling", "lbm_kernel_times", "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step",
             "lbm_steps_done", "lbm_free", "lbm_last_error"]
@@ -63,6 +64,7 @@ def lib():
         L.lbm_state_bytes.argtypes = [P(Params), P(sz)]
         L.lbm_init.argtypes = [P(Params), vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, sz, vp, P(vp)]
         L.lbm_step.argtypes = [vp, i32, vp]
+        L.lbm_step_async.argtypes = [vp, i32]
         L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lbm_populations.argtypes = [vp, vp, vp, vp]
         L.lbm_geometry.argtypes = [vp, vp, vp]
@@ -192,6 +194,10 @@ class Lbm:
             return None
         return np.frombuffer(out, dtype=np.float64).reshape(-1, 5)[:nsteps].copy()
 
+    def advance(self, nsteps=1):
+        """Enqueue nsteps on the stream without waiting (no reductions, no non-finite check)."""
+        self._check(lib().lbm_step_async(self._h, int(nsteps)), self._h)
+
     def _grid(self, t, comps=1):
         nx, ny, nz = self.shape
         return t.view(comps, nz, ny, nx) if comps > 1 else t.view(nz, ny, nx)
@@ -227,10 +233,14 @@ class Lbm:
         self.stream.synchronize()
         return info, wet.view(self.N, 4).t()
 
-    def get_state(self):
-        buf = self.torch.empty(self.state_bytes, dtype=self.torch.uint8, device=self.device)
+    def get_state(self, sync=True):
+        """A copy of the state (uint8 tensor of state_bytes). With sync=False the copy is only
+        enqueued on the context's stream (work on that stream sees it complete)."""
+        with self.torch.cuda.stream(self.stream):
+            buf = self.torch.empty(self.state_bytes, dtype=self.torch.uint8, device=self.device)
         self._check(lib().lbm_get_state(self._h, buf.data_ptr()), self._h)
-        self.stream.synchronize()
+        if sync:
+            self.stream.synchronize()
         return buf
 
     # ---- state layout and adjoint -------------------------------------------------------------
@@ -259,9 +269,12 @@ class Lbm:
         return f, a, g
 
     def adjoint_bytes(self):
-        ab, sb = ctypes.c_size_t(), ctypes.c_size_t()
-        self._check(lib().lbm_adjoint_bytes(ctypes.byref(self.params), ctypes.byref(ab), ctypes.byref(sb)), None)
-        return ab.value, sb.value
+        if getattr(self, "_adj_bytes", None) is None:
+            ab, sb = ctypes.c_size_t(), ctypes.c_size_t()
+            self._check(lib().lbm_adjoint_bytes(ctypes.byref(self.params), ctypes.byref(ab), ctypes.byref(sb)),
+                        None)
+            self._adj_bytes = (ab.value, sb.value)
+        return self._adj_bytes
 
     def new_adjoint(self):
         """A zeroed adjoint state: (30, P) tensor of the context's real type, P the plane stride;

@@ -394,7 +394,7 @@ StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
 }
 
 template <int P>
-lbm_status launch_step(lbm_ctx* c, int slot) {
+lbm_status launch_step(lbm_ctx* c, int slot, bool timed = true) {
   StepArgs<P> A = make_args<P>(c, c->cur);
   double* ring = reinterpret_cast<double*>(c->ws + c->L.ring);
   A.ring_row = ring + 5 * size_t(slot);
@@ -407,7 +407,7 @@ lbm_status launch_step(lbm_ctx* c, int slot) {
     hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlock), 0, c->stream, A.partials, c->nb_fluid, A.red_out);
   const dim3 grid(c->L.nblocks), block(kBlock);
   const dim3 gf(c->nb_fluid), ge(c->nb_ext);
-  hipEvent_t* ev = c->prof ? &c->ev[5 * size_t(slot)] : nullptr;
+  hipEvent_t* ev = (c->prof && timed) ? &c->ev[5 * size_t(slot)] : nullptr;
   if (ev) HIP_TRY(c, hipEventRecord(ev[0], c->stream));
   if (c->nb_fluid) hipLaunchKernelGGL(k_colour<P>, gf, block, 0, c->stream, A);
   if (ev) HIP_TRY(c, hipEventRecord(ev[1], c->stream));
@@ -749,6 +749,23 @@ lbm_status lbm_step(lbm_ctx* c, int32_t nsteps, lbm_reductions* per_step) {
     done += chunk;
   }
   if (bad) return fail(c, LBM_ERR_NONFINITE, "non-finite values after step %lld", (long long)c->steps);
+  return LBM_OK;
+}
+
+lbm_status lbm_step_async(lbm_ctx* c, int32_t nsteps) {
+  if (!c) return LBM_ERR_ARG;
+  if (nsteps < 0) return fail(c, LBM_ERR_ARG, "nsteps must be >= 0");
+  for (int t = 0; t < nsteps; ++t) {
+    lbm_status s;
+    const int slot = t % kRing;
+    switch (c->p.precision) {
+      case LBM_FP64: s = launch_step<0>(c, slot, false); break;
+      case LBM_FP32: s = launch_step<1>(c, slot, false); break;
+      case LBM_FP16_DEV: s = launch_step<2>(c, slot, false); break;
+      default: s = launch_step<3>(c, slot, false); break;
+    }
+    if (s != LBM_OK) return s;
+  }
   return LBM_OK;
 }
 

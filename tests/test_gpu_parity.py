@@ -251,6 +251,11 @@ def test_checkpoint_roundtrip_and_determinism(core, oracle_mod):
     assert a.steps_done == b.steps_done == 50
     assert np.array_equal(ra, rb)
     assert np.array_equal(a.get_state().cpu().numpy(), b.get_state().cpu().numpy())
+    # the enqueue-only entry point runs the same kernels
+    c = core.Lbm(shape, solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision="fp32", **kw)
+    c.advance(50)
+    assert c.steps_done == 50
+    assert np.array_equal(a.get_state().cpu().numpy(), c.get_state(sync=False).cpu().numpy())
 
 
 def test_nonfinite_is_reported(core):
