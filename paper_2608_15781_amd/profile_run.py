@@ -40,9 +40,22 @@ def run_adjoint(args):
     steps = args.steps
     L, cps, final = ag.forward_states(sim, steps, w["checkpoint"])
     gth, gxi, _ = ag.adjoint_gradients(sim, steps, w["checkpoint"], cps, final)
+    res = dict(workload="adjoint96", precision=args.precision, steps=steps, fluid_nodes=int((solid == 0).sum()),
+               L=L, dxi=float(gxi))
     torch.cuda.synchronize()
-    print(json.dumps(dict(workload="adjoint96", precision=args.precision, steps=steps,
-                          fluid_nodes=int((solid == 0).sum()), L=L, dxi=float(gxi))), flush=True)
+    _calibration_copy(args, torch)  # the last dispatch of the run
+    print(json.dumps(res), flush=True)
+
+
+def _calibration_copy(args, torch):
+    """A plain device copy of known size, with its source evicted from the last-level cache."""
+    n = args.copy_mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    flush = torch.ones(2 * n, dtype=torch.float32, device="cuda:0")
+    del flush
+    dst.copy_(src)
+    torch.cuda.synchronize()
 
 
 def run(args):
@@ -58,16 +71,9 @@ def run(args):
     sim.step(args.warmup, reductions=False)
     sim.step(args.steps)
     torch.cuda.synchronize()
-    n = args.copy_mib * (1 << 20) // 4
-    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
-    dst = torch.empty_like(src)
-    # evict the source from the 256 MB last-level cache before the calibration copy
-    flush = torch.ones(2 * n, dtype=torch.float32, device="cuda:0")
-    del flush
-    dst.copy_(src)
-    torch.cuda.synchronize()
+    _calibration_copy(args, torch)
     print(json.dumps(dict(workload=args.workload, precision=args.precision, steps=args.steps,
-                          fluid_nodes=int((solid == 0).sum()), copy_bytes=4 * n)), flush=True)
+                          fluid_nodes=int((solid == 0).sum()), copy_bytes=args.copy_mib << 20)), flush=True)
 
 
 def _rows(pattern):
@@ -137,17 +143,20 @@ def report(args):
     fe = summarize(args.fetch, copy_bytes)["counters"]["FETCH_SIZE"]
     wr = summarize(args.write, copy_bytes)["counters"]["WRITE_SIZE"]
     fluid = args.fluid_nodes
-    lines = ["# Step kernels, %s, %s storage" % (args.workload, args.precision), "",
+    adj = args.mode == "adjoint"
+    drv = "python3 -m paper_2608_15781_amd.profile_run %s--precision %s --steps " % ("adjoint " if adj else "",
+                                                                                    args.precision)
+    steps = (200, 40) if adj else (50, 20)
+    title = ("Adjoint kernels, adjoint96 (forward with checkpoints every 20 steps, then the checkpointed backward)"
+             if adj else "Step kernels, %s" % args.workload)
+    lines = ["# %s, %s storage" % (title, args.precision), "",
              "Commands (repository root, `cd /tmp && export TMPDIR=/tmp` first, `PYTHONPATH` = repository root):", "",
              "```",
-             "rocprofv3 --kernel-trace --stats --output-format csv -d OUT/prof -o run -- "
-             "python3 -m paper_2608_15781_amd.profile_run --precision %s --steps 50" % args.precision,
-             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o run -- "
-             "python3 -m paper_2608_15781_amd.profile_run --precision %s --steps 20" % args.precision,
-             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o run -- "
-             "python3 -m paper_2608_15781_amd.profile_run --precision %s --steps 20" % args.precision,
-             "python3 -m paper_2608_15781_amd.profile_run report --precision %s --fluid-nodes %d "
-             "OUT/prof OUT/fetch OUT/write" % (args.precision, fluid),
+             "rocprofv3 --kernel-trace --stats --output-format csv -d OUT/prof -o run -- %s%d" % (drv, steps[0]),
+             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o run -- %s%d" % (drv, steps[1]),
+             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o run -- %s%d" % (drv, steps[1]),
+             "python3 -m paper_2608_15781_amd.profile_run report %s--precision %s --fluid-nodes %d "
+             "OUT/prof OUT/fetch OUT/write" % ("--mode adjoint " if adj else "", args.precision, fluid),
              "```", "",
              "Counter calibration: the run ends with a %d MiB device copy (source evicted from the last-level "
              "cache first); it reads FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB for %.0f KiB moved each way, "
@@ -168,10 +177,18 @@ def report(args):
         traffic[name] = b
         lines.append("| `%s` | %d | %.2f | %.2f | %.1f | %.1f | %.2f | %.1f | %.0f |" % (
             name, k["calls"], k["avg_us"], k["min_us"], f, w, b / 1e6, b / fluid, b / (k["avg_us"] * 1e3)))
-    step_us = sum(k["avg_us"] for n, k in kt.items() if n.startswith("lbm::"))
-    step_b = sum(traffic.values())
-    lines += ["", "Fluid nodes: %d. Sum over the step kernels: %.2f us, %.1f MB, %.1f B per fluid node." % (
-        fluid, step_us, step_b / 1e6, step_b / fluid), "",
+    if adj:
+        nsteps = kt["lbm::k_adj_collide<%d>" % {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}[args.precision]]["calls"]
+        tot = sum(k["avg_us"] * k["calls"] for n, k in kt.items() if n.startswith("lbm::"))
+        lines += ["", "Fluid nodes: %d. Library kernel time per adjoint step (all launches of the run, forward "
+                  "recomputation included, divided by the %d adjoint steps): %.1f us." % (fluid, nsteps, tot / nsteps),
+                  ""]
+    else:
+        step_us = sum(k["avg_us"] for n, k in kt.items() if n.startswith("lbm::"))
+        step_b = sum(traffic.values())
+        lines += ["", "Fluid nodes: %d. Sum over the step kernels: %.2f us, %.1f MB, %.1f B per fluid node." % (
+            fluid, step_us, step_b / 1e6, step_b / fluid), ""]
+    lines += [
         "Machine-readable (read by bench.py; valid only while the HIP sources hash to the digest):", "",
         "- source_digest: %s" % build.source_digest()]
     for name, b in traffic.items():
@@ -186,6 +203,7 @@ def main():
     ap.add_argument("fetch", nargs="?")
     ap.add_argument("write", nargs="?")
     ap.add_argument("--fluid-nodes", type=int, default=0)
+    ap.add_argument("--mode", default="step", choices=["step", "adjoint"])
     ap.add_argument("--workload", default="bijel128")
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--steps", type=int, default=50)
