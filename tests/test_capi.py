@@ -51,6 +51,27 @@ def test_workspace_sizes_scale_with_precision(core):
     assert sizes["fp16"][1] < sizes["fp32"][1] < sizes["fp64"][1]
 
 
+@pytest.mark.parametrize("species", [True, False])
+@pytest.mark.parametrize("prec,s,r", [("fp64", 8, 8), ("fp32", 4, 4), ("fp16", 2, 4), ("bf16", 2, 4)])
+def test_state_layout_and_plane_stride(core, prec, s, r, species):
+    """The population planes, colour scalars and species planes fit in the reported state size, and
+    planes are an odd multiple of 256 bytes apart (equal entries of different planes do not share
+    a memory channel when N is a power of two)."""
+    N = 64 ** 3
+    p = core.make_params((64, 64, 64), precision=prec, tau=0.8, species=species)
+    f, a, g, ps = (ctypes.c_size_t() for _ in range(4))
+    assert core.lib().lbm_state_layout(ctypes.byref(p), ctypes.byref(f), ctypes.byref(a), ctypes.byref(g),
+                                       ctypes.byref(ps)) == 0
+    assert ps.value >= N and (ps.value * s) % 256 == 0 and (ps.value * s // 256) % 2 == 1
+    assert f.value == 0 and a.value >= 19 * s * ps.value and g.value >= a.value + 4 * r * ps.value
+    sb = ctypes.c_size_t()
+    assert core.lib().lbm_state_bytes(ctypes.byref(p), ctypes.byref(sb)) == 0
+    assert sb.value >= g.value + (7 * s * ps.value if species else 0)
+    ab, scr = ctypes.c_size_t(), ctypes.c_size_t()
+    assert core.lib().lbm_adjoint_bytes(ctypes.byref(p), ctypes.byref(ab), ctypes.byref(scr)) == 0
+    assert ab.value >= 30 * r * ps.value
+
+
 @pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("sigma", -1.0), ("beta", -0.1),
                                          ("xi", -1e-3), ("grad_eps", 0.0), ("nx", 0), ("precision", 7),
                                          ("reserved", 1), ("fp16_scale_log2", 40)])
