@@ -181,6 +181,16 @@ lbm_status lbm_kernel_times(lbm_ctx* ctx, double* kernel_ms, int64_t* steps);
  * lbm_adjoint_step needs (both caller-owned device memory). */
 lbm_status lbm_adjoint_bytes(const lbm_params* params, size_t* adj_bytes, size_t* scratch_bytes);
 
+/* Size of a buffer for the forward fields of one level (rho^N, the realigned normal n* with
+ * |grad rho^N|, rho^m), for lbm_step_fields and lbm_adjoint_step_fields. */
+lbm_status lbm_fields_bytes(const lbm_params* params, size_t* bytes);
+
+/* One time step, enqueued like lbm_step_async, that computes its level-t fields (the state
+ * before the step) in d_fields (device memory of lbm_fields_bytes, caller-owned) instead of the
+ * context's workspace. Same kernels and results as lbm_step. For checkpoint recomputation:
+ * lbm_adjoint_step_fields then reuses the fields instead of recomputing them. */
+lbm_status lbm_step_fields(lbm_ctx* ctx, void* d_fields);
+
 /* Writes dL/dS_T for L = m^p(T) into d_adj, given the state d_state (lbm_state_bytes, as from
  * lbm_get_state) of level T. Stream-ordered. */
 lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const void* d_state, void* d_adj);
@@ -196,6 +206,12 @@ lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const void* d_state, void* d_adj);
  * null or aliased buffers, LBM_ERR_HIP. */
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* d_state, const void* d_adj_in, void* d_adj_out,
                             void* d_scratch, double* d_grad_theta, double* d_grad_xi);
+
+/* lbm_adjoint_step with the level-t fields of d_state taken from d_fields (as written by
+ * lbm_step_fields from the same state) instead of recomputed; otherwise identical, bit for
+ * bit. Errors as lbm_adjoint_step. */
+lbm_status lbm_adjoint_step_fields(lbm_ctx* ctx, const void* d_state, const void* d_fields, const void* d_adj_in,
+                                   void* d_adj_out, void* d_scratch, double* d_grad_theta, double* d_grad_xi);
 
 /* Number of steps taken since init (or the value given to lbm_set_state). */
 int64_t lbm_steps_done(const lbm_ctx* ctx);

@@ -44,25 +44,35 @@ def forward_states(sim, steps, checkpoint):
     return conv, cps, sim.get_state()
 
 
-def adjoint_gradients(sim, steps, checkpoint, cps, final_state):
-    """Reverse sweep with checkpoint-and-recompute; returns (dL/dtheta per node, dL/dxi)."""
+def adjoint_gradients(sim, steps, checkpoint, cps, final_state, keep_fields=True):
+    """Reverse sweep with checkpoint-and-recompute; returns (dL/dtheta per node, dL/dxi, lambda_0).
+
+    Each segment is recomputed from its checkpoint with enqueue-only steps; with keep_fields the
+    recomputation also keeps every level's rho^N, n* and rho^m (lbm_step_fields), which the
+    adjoint steps then reuse instead of recomputing (same values bit for bit)."""
     dev = sim.device
     lam = sim.new_adjoint()
     lam2 = sim.new_adjoint()
     scratch = sim.new_scratch()
     gth = torch.zeros(sim.N, dtype=torch.float64, device=dev)
     gxi = torch.zeros(1, dtype=torch.float64, device=dev)
+    fields = [sim.new_fields() for _ in range(checkpoint)] if keep_fields else None
     sim.adjoint_seed(final_state, lam)
     starts = sorted(cps)
     for s0 in reversed(starts):
         s1 = min(s0 + checkpoint, steps)
         sim.set_state(cps[s0], s0)
         seg = [cps[s0]]
-        for _ in range(s0, s1 - 1):
-            sim.advance(1)  # stream-ordered: no host round trip inside the segment
-            seg.append(sim.get_state(sync=False))
+        for t in range(s0, s1):
+            if keep_fields:
+                sim.step_fields(fields[t - s0])  # S_t -> S_{t+1}, keeping the fields of level t
+            elif t < s1 - 1:
+                sim.advance(1)  # stream-ordered: no host round trip inside the segment
+            if t < s1 - 1:
+                seg.append(sim.get_state(sync=False))
         for t in range(s1 - 1, s0 - 1, -1):
-            sim.adjoint_step(seg[t - s0], lam, lam2, scratch, gth, gxi)
+            sim.adjoint_step(seg[t - s0], lam, lam2, scratch, gth, gxi,
+                             fields=fields[t - s0] if keep_fields else None)
             lam, lam2 = lam2, lam
         del seg
     torch.cuda.synchronize(dev)

@@ -20,7 +20,8 @@ EXPORTED = ["lbm_version", "lbm_workspace_bytes", "lbm_state_bytes", "lbm_init",
             "lbm_moments",
             "lbm_populations", "lbm_geometry", "lbm_state_layout", "lbm_get_state", "lbm_set_state",
             "lbm_set_profiling", "lbm_kernel_times", "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step",
-            "lbm_steps_done", "lbm_free", "lbm_last_error"]
+            "lbm_steps_done", "lbm_free", "lbm_last_error", "lbm_fields_bytes", "lbm_step_fields",
+            "lbm_adjoint_step_fields"]
 KERNELS = ("colour", "extrap", "normal", "collide")
 
 
@@ -65,6 +66,9 @@ def lib():
         L.lbm_init.argtypes = [P(Params), vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, sz, vp, P(vp)]
         L.lbm_step.argtypes = [vp, i32, vp]
         L.lbm_step_async.argtypes = [vp, i32]
+        L.lbm_fields_bytes.argtypes = [P(Params), P(sz)]
+        L.lbm_step_fields.argtypes = [vp, vp]
+        L.lbm_adjoint_step_fields.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lbm_populations.argtypes = [vp, vp, vp, vp]
         L.lbm_geometry.argtypes = [vp, vp, vp]
@@ -307,7 +311,23 @@ class Lbm:
         self._check_adjoint_args(state, adj)
         self._check(lib().lbm_adjoint_seed(self._h, state.data_ptr(), adj.data_ptr()), self._h)
 
-    def adjoint_step(self, state, adj_in, adj_out, scratch, grad_theta, grad_xi):
+    def fields_bytes(self):
+        if getattr(self, "_fields_bytes", None) is None:
+            b = ctypes.c_size_t()
+            self._check(lib().lbm_fields_bytes(ctypes.byref(self.params), ctypes.byref(b)), None)
+            self._fields_bytes = b.value
+        return self._fields_bytes
+
+    def new_fields(self):
+        """A buffer for the forward fields of one level (lbm_step_fields)."""
+        return self.torch.empty(self.fields_bytes(), dtype=self.torch.uint8, device=self.device)
+
+    def step_fields(self, fields):
+        """One enqueued step that keeps its level-t fields in `fields` (from new_fields)."""
+        self._need(fields, self.fields_bytes(), "fields")
+        self._check(lib().lbm_step_fields(self._h, fields.data_ptr()), self._h)
+
+    def adjoint_step(self, state, adj_in, adj_out, scratch, grad_theta, grad_xi, fields=None):
         """adj_out <- (dS_{t+1}/dS_t)^T adj_in at the state S_t; accumulates grad_theta (N doubles) and
         grad_xi (1 double) on the device."""
         if grad_theta.dtype != self.torch.float64 or grad_xi.dtype != self.torch.float64:
@@ -316,9 +336,15 @@ class Lbm:
         self._need(grad_theta, 8 * self.N, "grad_theta")
         self._need(grad_xi, 8, "grad_xi")
         self._need(scratch, self.adjoint_bytes()[1] + 255, "scratch")
-        self._check(lib().lbm_adjoint_step(self._h, state.data_ptr(), adj_in.data_ptr(), adj_out.data_ptr(),
-                                           ctypes.c_void_p(self._aligned(scratch)), grad_theta.data_ptr(),
-                                           grad_xi.data_ptr()), self._h)
+        if fields is None:
+            self._check(lib().lbm_adjoint_step(self._h, state.data_ptr(), adj_in.data_ptr(), adj_out.data_ptr(),
+                                               ctypes.c_void_p(self._aligned(scratch)), grad_theta.data_ptr(),
+                                               grad_xi.data_ptr()), self._h)
+        else:
+            self._need(fields, self.fields_bytes(), "fields")
+            self._check(lib().lbm_adjoint_step_fields(self._h, state.data_ptr(), fields.data_ptr(), adj_in.data_ptr(),
+                                                      adj_out.data_ptr(), ctypes.c_void_p(self._aligned(scratch)),
+                                                      grad_theta.data_ptr(), grad_xi.data_ptr()), self._h)
 
     def set_profiling(self, enable: bool):
         self._check(lib().lbm_set_profiling(self._h, int(bool(enable))), self._h)

@@ -83,6 +83,24 @@ struct AdjLayout {
   size_t lrn, lnc, lglen, lH, lG, lrr, lrm, lgo, rmv, partials, sum, total;  // scratch offsets
 };
 
+// Forward fields of one level, kept by lbm_step_fields for lbm_adjoint_step_fields: rho^N (dense),
+// n* and |G| (per fluid id), rho^m (dense).
+struct FieldLayout {
+  size_t rhoN, nst, rm, total;
+};
+
+FieldLayout make_field_layout(const lbm_params& p) {
+  FieldLayout F{};
+  const size_t N = size_t(p.nx) * p.ny * p.nz;
+  const size_t r = real_bytes(p.precision);
+  size_t o = 0;
+  F.rhoN = o; o = align_up(o + r * N);
+  F.nst = o; o = align_up(o + 4 * r * N);
+  F.rm = o; o = align_up(o + r * N);
+  F.total = o;
+  return F;
+}
+
 AdjLayout make_adj_layout(const lbm_params& p) {
   AdjLayout A{};
   const size_t N = size_t(p.nx) * p.ny * p.nz;
@@ -394,8 +412,16 @@ StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
 }
 
 template <int P>
-lbm_status launch_step(lbm_ctx* c, int slot, bool timed = true) {
+lbm_status launch_step(lbm_ctx* c, int slot, bool timed = true, void* fields = nullptr) {
+  using R = typename Prec<P>::R;
   StepArgs<P> A = make_args<P>(c, c->cur);
+  if (fields) {  // this step's rho^N, n*, |G| and rho^m go to the caller's buffer
+    const FieldLayout FL = make_field_layout(c->p);
+    char* fb = static_cast<char*>(fields);
+    A.rhoN = reinterpret_cast<R*>(fb + FL.rhoN);
+    A.nst = reinterpret_cast<R*>(fb + FL.nst);
+    A.rm_out = reinterpret_cast<R*>(fb + FL.rm);
+  }
   double* ring = reinterpret_cast<double*>(c->ws + c->L.ring);
   A.ring_row = ring + 5 * size_t(slot);
   // The previous step's partials are summed by k_normal of this step (its workgroup 0); the
@@ -536,13 +562,20 @@ lbm_status launch_adj_seed(lbm_ctx* c, const void* state, void* adj) {
 }
 
 template <int P>
-lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* lin, void* lout, void* scratch, double* gth,
-                           double* gxi) {
+lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* fields, const void* lin, void* lout,
+                           void* scratch, double* gth, double* gxi) {
   using R = typename Prec<P>::R;
   const AdjLayout AL = make_adj_layout(c->p);
   char* sc = static_cast<char*>(scratch);
   StepArgs<P> A = make_args_from<P>(c, state);
   A.rm_out = reinterpret_cast<R*>(sc + AL.rmv);
+  if (fields) {  // level-t fields kept by the forward step: no recomputation
+    const FieldLayout FL = make_field_layout(c->p);
+    char* fb = const_cast<char*>(static_cast<const char*>(fields));
+    A.rhoN = reinterpret_cast<R*>(fb + FL.rhoN);
+    A.nst = reinterpret_cast<R*>(fb + FL.nst);
+    A.rm_out = reinterpret_cast<R*>(fb + FL.rm);
+  }
   AdjArgs<R> J;
   J.lin = static_cast<const R*>(lin);
   J.lout = static_cast<R*>(lout);
@@ -562,9 +595,11 @@ lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* lin, void*
   J.gxi = gxi;
   const dim3 gf(c->nb_fluid), ge(c->nb_ext), block(kBlock);
   // Forward fields of level t.
-  if (c->nb_fluid) hipLaunchKernelGGL(k_colour<P>, gf, block, 0, c->stream, A);
-  if (c->nb_ext) hipLaunchKernelGGL(k_extrap<P>, ge, block, 0, c->stream, A);
-  if (c->nb_fluid) hipLaunchKernelGGL(k_normal<P>, gf, block, 0, c->stream, A);
+  if (!fields) {
+    if (c->nb_fluid) hipLaunchKernelGGL(k_colour<P>, gf, block, 0, c->stream, A);
+    if (c->nb_ext) hipLaunchKernelGGL(k_extrap<P>, ge, block, 0, c->stream, A);
+    if (c->nb_fluid) hipLaunchKernelGGL(k_normal<P>, gf, block, 0, c->stream, A);
+  }
   // Reverse pass. Every entry of lout a fluid node owns is written (see k_adj_collide).
   if (c->nb_fluid) {
     hipLaunchKernelGGL(k_adj_collide<P>, gf, block, 0, c->stream, A, J);
@@ -769,6 +804,24 @@ lbm_status lbm_step_async(lbm_ctx* c, int32_t nsteps) {
   return LBM_OK;
 }
 
+lbm_status lbm_fields_bytes(const lbm_params* params, size_t* bytes) {
+  lbm_status s = check_params(params, g_err, sizeof(g_err));
+  if (s != LBM_OK) return s;
+  if (bytes) *bytes = make_field_layout(*params).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_step_fields(lbm_ctx* c, void* d_fields) {
+  if (!c) return LBM_ERR_ARG;
+  if (!d_fields) return fail(c, LBM_ERR_ARG, "a fields buffer is required");
+  switch (c->p.precision) {
+    case LBM_FP64: return launch_step<0>(c, 0, false, d_fields);
+    case LBM_FP32: return launch_step<1>(c, 0, false, d_fields);
+    case LBM_FP16_DEV: return launch_step<2>(c, 0, false, d_fields);
+    default: return launch_step<3>(c, 0, false, d_fields);
+  }
+}
+
 lbm_status lbm_moments(lbm_ctx* c, void* rr, void* rp, void* rn, void* u, void* cc) {
   if (!c) return LBM_ERR_ARG;
   DISPATCH(c, launch_moments, rr, rp, rn, u, cc);
@@ -866,7 +919,17 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* d_state, const void* d_adj_i
   if (!d_state || !d_adj_in || !d_adj_out || !d_scratch || !d_grad_theta || !d_grad_xi)
     return fail(c, LBM_ERR_ARG, "all buffers are required");
   if (d_adj_in == d_adj_out) return fail(c, LBM_ERR_ARG, "adjoint input and output must differ");
-  DISPATCH(c, launch_adj_step, d_state, d_adj_in, d_adj_out, d_scratch, d_grad_theta, d_grad_xi);
+  const void* no_fields = nullptr;
+  DISPATCH(c, launch_adj_step, d_state, no_fields, d_adj_in, d_adj_out, d_scratch, d_grad_theta, d_grad_xi);
+}
+
+lbm_status lbm_adjoint_step_fields(lbm_ctx* c, const void* d_state, const void* d_fields, const void* d_adj_in,
+                                   void* d_adj_out, void* d_scratch, double* d_grad_theta, double* d_grad_xi) {
+  if (!c) return LBM_ERR_ARG;
+  if (!d_state || !d_fields || !d_adj_in || !d_adj_out || !d_scratch || !d_grad_theta || !d_grad_xi)
+    return fail(c, LBM_ERR_ARG, "all buffers are required");
+  if (d_adj_in == d_adj_out) return fail(c, LBM_ERR_ARG, "adjoint input and output must differ");
+  DISPATCH(c, launch_adj_step, d_state, d_fields, d_adj_in, d_adj_out, d_scratch, d_grad_theta, d_grad_xi);
 }
 
 int64_t lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }

@@ -137,11 +137,14 @@ def test_gradient_matches_oracle_duals_and_checkpointing(core, oracle_mod):
     assert abs(Lg - L) < 1e-10 * abs(L)
     for a, b in zip(ad, dL):
         assert abs(a - b) < 1e-8 * abs(b) + 1e-14, (a, b)
-    # checkpoint-and-recompute (every 7 steps) reproduces the gradient exactly
+    # checkpoint-and-recompute (every 7 steps) reproduces the gradient exactly, and so does
+    # recomputing the level fields inside each adjoint step instead of keeping them
     sim2 = _sim(core, n, solid, theta, rr0, rp0, xi)
     L2, cps2, final2 = ag.forward_states(sim2, T, 7)
     gth2, gxi2, _ = ag.adjoint_gradients(sim2, T, 7, cps2, final2)
     assert torch.equal(gth2, gth) and float(gxi2) == float(gxi)
+    gth3, gxi3, _ = ag.adjoint_gradients(sim2, T, 7, cps2, final2, keep_fields=False)
+    assert torch.equal(gth3, gth) and float(gxi3) == float(gxi)
     # the autograd function
     th_t = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
     xi_t = torch.tensor(xi, dtype=torch.float64, requires_grad=True)
