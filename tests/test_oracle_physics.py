@@ -126,6 +126,34 @@ def test_species_decay_matches_fourier_evolution(oracle_mod):
     assert abs(amp / (A * np.exp(-D * k * k * T)) - 1) < 0.02
 
 
+def test_species_inlet_and_outflow_diffusion(oracle_mod):
+    """Species at rest entering through the inlet plane (C = C_in at x = 0) into C = 0, with the
+    zero-gradient outflow plane at x = L-1 (reading of the design notes): C follows the series
+    solution of C_t = D C_xx with C(0) = 1 and C_x(L - 1/2) = 0, to first order in the lattice
+    spacing (the error halves when L doubles at fixed D t / L^2). A Dirichlet point half a node
+    off, or the outflow condition at L - 1 or L, fits worse."""
+    tau_c = 0.9
+    D = (tau_c - 0.5) / 4
+
+    def err(L, T, x0=0.0, Lb=None):
+        o = oracle_mod.Oracle((L, 1, 1), rho_r0=1.0, rho_p0=0.0, c0=np.zeros(L), species=True, x_open=True,
+                              tau_c=tau_c, c_in=1.0)
+        o.step(T)
+        C = o.moments()["c"][0, 0, :]
+        x = np.arange(L, dtype=float)
+        Lb = L - 0.5 if Lb is None else Lb
+        k = np.arange(4000)
+        lam = (2 * k + 1) * np.pi / (2 * (Lb - x0))
+        ser = 1 - (4 / ((2 * k + 1) * np.pi) * np.sin(np.outer(x - x0, lam)) * np.exp(-D * lam ** 2 * T)).sum(1)
+        assert C[0] == 1.0
+        return np.abs(C[1:] - ser[1:]).max()
+
+    e40, e80 = err(40, 6000), err(80, 24000)
+    assert e40 < 6e-3 and e80 < 3e-3 and e80 < 0.6 * e40, (e40, e80)
+    for x0, Lb in ((0.0, 79.0), (0.0, 80.0), (0.5, 79.5), (-0.5, 79.5)):
+        assert err(80, 24000, x0, Lb) > 1.4 * e80, (x0, Lb)
+
+
 def _grf_case(n=16, wavelength=8.0, seed=7):
     solid, _ = inputs.grf_mask((n, n, n), wavelength, seed)
     return solid
