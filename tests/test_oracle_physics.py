@@ -154,6 +154,34 @@ def test_species_inlet_and_outflow_diffusion(oracle_mod):
         assert err(80, 24000, x0, Lb) > 1.4 * e80, (x0, Lb)
 
 
+def test_solid_normal_flat_walls_and_sphere(oracle_mod):
+    """E8 solid normal (eq. normal_vector_solid) at wetting nodes: exactly the wall normal,
+    pointing into the solid, next to a flat wall of each orientation; within the staircase error
+    of the radial direction next to a voxelised sphere."""
+    n = 16
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    for axis, coord in enumerate((x, y, z)):
+        solid = (coord < 3).astype(np.uint8)
+        g = oracle_mod.Oracle((n, n, n), solid=solid).geometry()
+        ok = g["ns_ok"].astype(bool) & (solid.ravel() == 0)
+        lo = coord.ravel()[ok] == 3      # solid below: normal points to -axis
+        hi = coord.ravel()[ok] == n - 1  # periodic image of the solid above
+        assert lo.sum() == n * n and hi.sum() == n * n and (lo | hi).all()
+        e = np.zeros(3)
+        e[axis] = 1.0
+        assert np.abs(g["ns"][:, ok][:, lo] + e[:, None]).max() < 1e-15
+        assert np.abs(g["ns"][:, ok][:, hi] - e[:, None]).max() < 1e-15
+    c = 7.5
+    r = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
+    solid = (r < 4.5).astype(np.uint8)
+    g = oracle_mod.Oracle((n, n, n), solid=solid).geometry()
+    ok = g["ns_ok"].astype(bool) & (solid.ravel() == 0)
+    d = np.stack([(c - a).ravel()[ok] for a in (x, y, z)])
+    d /= np.linalg.norm(d, axis=0)
+    ang = np.degrees(np.arccos(np.clip((g["ns"][:, ok] * d).sum(0), -1, 1)))
+    assert ok.sum() > 300 and ang.mean() < 10 and ang.max() < 20, (ang.mean(), ang.max())
+
+
 def _grf_case(n=16, wavelength=8.0, seed=7):
     solid, _ = inputs.grf_mask((n, n, n), wavelength, seed)
     return solid
