@@ -151,8 +151,9 @@ def main():
     ap.add_argument("--modes", default="fp16,bf16", help="extra storage precisions to time")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (domain decomposition "
-              "across GPUs is described in the design notes but not implemented).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (the step would shard by "
+              "spatial domain decomposition with face exchanges between GPUs; that is not implemented).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -316,8 +316,9 @@ __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs<P> A) {
 
 // ---------------------------------------------------------------------------------------------
 // normal: G = 3 sum_i w_i c_i rho^N(x + c_i) as pair differences (a uniform field gives exactly
-// zero), n = +G/|G| (sign: see the design notes; with it force, curvature, recolouring and the
-// wetting angle all act with the physical sign), and at wetting nodes the Akai realignment
+// zero), n = +G/|G| (the opposite of the sign printed in eq. color_gradient_normal: with +G the
+// force, curvature, recolouring and wetting angle all act with the physical sign, theta measured
+// through the reactant colour), and at wetting nodes the Akai realignment
 // n* = n+ (n+ is always at least as close to n as n-: n+.n - n-.n = 2 sin(theta) sin(theta')).
 // ---------------------------------------------------------------------------------------------
 template <int P>

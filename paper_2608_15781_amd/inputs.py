@@ -87,9 +87,9 @@ def crop(a, size):
     return np.ascontiguousarray(a[:size, :size, :size])
 
 
-# Workloads used by the tests and the benchmark, named by what they are. Unstated physical
-# parameters take the values listed in the design notes (tau = 0.8, sigma = 0.01, tau_C = 0.9,
-# C_in = C_0 = 1, beta = 0.7, all-reactant start).
+# Workloads used by the tests and the benchmark, named by what they are. Physical parameters
+# the paper leaves unstated take these values: tau = 0.8 (kinematic viscosity 0.1),
+# sigma = 0.01, tau_C = 0.9, C_in = C_0 = 1, beta = 0.7, all-reactant start.
 WORKLOADS = {
     "droplet32": dict(shape=(32, 32, 32), radius=8.0, tau=1.0, sigma=0.01, beta=0.7, steps=500,
                       precision="fp64", species=False, xi=0.0),

@@ -128,7 +128,7 @@ def test_species_decay_matches_fourier_evolution(oracle_mod):
 
 def test_species_inlet_and_outflow_diffusion(oracle_mod):
     """Species at rest entering through the inlet plane (C = C_in at x = 0) into C = 0, with the
-    zero-gradient outflow plane at x = L-1 (reading of the design notes): C follows the series
+    zero-gradient outflow plane at x = L-1 (the outflow node takes its own S_1): C follows the series
     solution of C_t = D C_xx with C(0) = 1 and C_x(L - 1/2) = 0, to first order in the lattice
     spacing (the error halves when L doubles at fixed D t / L^2). A Dirichlet point half a node
     off, or the outflow condition at L - 1 or L, fits worse."""
