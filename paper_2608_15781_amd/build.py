@@ -36,13 +36,18 @@ def build(verbose: bool = False) -> str:
 
 
 def source_digest() -> str:
-    """SHA-256 over the HIP sources and headers (identifies the kernels a profile was taken on)."""
+    """SHA-256 over the HIP sources and headers with comments and blank space removed (identifies
+    the kernels a profile was taken on; editing a comment does not change it)."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for p in SOURCES + HEADERS:
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
