@@ -1,0 +1,68 @@
+"""Reactor pipeline on the GPU: single-phase permeability of a slit against the plane-Poiseuille
+closed form, and the paper's reaction set-up (nucleation sites, xi = 1, sigma = 0.3, paper mode
+without species) against the oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def core():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_15781_amd import core as c
+
+    c.lib()
+    return c
+
+
+def test_slit_permeability_matches_plane_poiseuille(core):
+    """Fluid layers z = 1..H between periodic solid layers z = 0: with halfway bounce-back the
+    walls sit half a node outside the fluid, the mean fluid velocity is a H^2 / (12 nu), and the
+    superficial (whole-lattice) permeability is phi H^2 / 12 with phi = H / nz."""
+    from paper_2608_15781_amd import reactor
+
+    nz, H = 18, 17
+    solid = np.zeros((nz, 6, 8), np.uint8)
+    solid[0] = 1
+    for axis in (0, 1):
+        kappa, u, steps = reactor.permeability(core, solid, axis=axis, accel=1e-6, nu=0.1, rtol=1e-9)
+        expect = (H / nz) * H * H / 12.0
+        print("slit axis %d: kappa %.6f closed form %.6f (%d steps)" % (axis, kappa, expect, steps), flush=True)
+        assert abs(kappa / expect - 1) < 5e-3
+
+
+def test_paper_reaction_setup_against_oracle(core, oracle_mod):
+    """24^3 random-field mask with one nucleation site per 12^3 block, xi = 1 (full conversion at a
+    site), sigma = 0.3, beta = 0.7, body force from Bo_p = 0.01, tau from Da = 1 (kappa taken as
+    1), contact angle 60 deg, FP64, 150 steps: per-step m^r, m^p and conversion, and the fields,
+    against the oracle; the effectiveness factor of the first step is 1 (all-reactant start)."""
+    from paper_2608_15781_amd import inputs, reactor
+
+    n = 24
+    solid, _ = inputs.grf_mask((n, n, n), 8.0, 11)
+    st = reactor.reaction_setup(solid, da=1.0, theta_deg=60.0, kappa=1.0, block=12, seed=4)
+    assert len(st["sites"]) == 8 and st["area_r"] == 8
+    a = (st["accel"], 0.0, 0.0)
+    kw = dict(theta=st["theta"], reactive=st["reactive"], rho_r0=(1 - solid).astype(float), rho_p0=0.0,
+              tau=st["tau"], sigma=st["sigma"], beta=st["beta"], xi=st["xi"], accel=[a, a], species=False)
+    sim = core.Lbm((n, n, n), solid=solid, precision="fp64", **kw)
+    ref = oracle_mod.Oracle((n, n, n), solid=solid, **kw)
+    T = 150
+    rg = sim.step(T)
+    rr = ref.step(T)
+    for j in (0, 1, 2):
+        assert np.abs(rg[:, j] - rr[:, j]).max() <= 1e-10 * np.abs(rr[:, j]).max(), j
+    m = sim.moments()
+    mr = ref.moments()
+    for key in ("rho_r", "rho_p", "rho_n", "u"):
+        g = m[key].cpu().numpy()
+        assert np.abs(g - mr[key]).max() <= 1e-10 * np.abs(mr[key]).max(), key
+    geo = st["geometry"]
+    alpha, mean = reactor.effectiveness(rg[:, 0], rg[:, 2], st["xi"], st["area_r"], geo["phi"], geo["V"])
+    assert abs(alpha[0] - 1) < 1e-12
+    print("paper set-up: tau %.4f a %.3e; alpha(0) %.6f, mean alpha over %d steps %.4f" %
+          (st["tau"], st["accel"], alpha[0], T, mean[-1]), flush=True)
