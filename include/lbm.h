@@ -191,6 +191,18 @@ lbm_status lbm_fields_bytes(const lbm_params* params, size_t* bytes);
  * lbm_adjoint_step_fields then reuses the fields instead of recomputing them. */
 lbm_status lbm_step_fields(lbm_ctx* ctx, void* d_fields);
 
+/* One time step (the composite update of Sec. 2: streaming, colour gradient and wetting,
+ * forcing, central-moment collision, recolouring, wall reaction, species) from the state in
+ * d_src to the state in d_dst, both caller-owned device buffers of lbm_state_bytes in the layout
+ * of lbm_get_state. The context's own state and step count are left as they are; its geometry,
+ * parameters and per-step workspace fields are used. d_fields: NULL, or a buffer of
+ * lbm_fields_bytes that receives the level-t fields of d_src as lbm_step_fields writes them.
+ * Enqueued only, like lbm_step_async: no reductions, no non-finite report. Results are bitwise
+ * those of lbm_step from the same state. For checkpoint recomputation that keeps every level
+ * without copying states. Errors: LBM_ERR_ARG for NULL states or overlapping buffers,
+ * LBM_ERR_HIP. */
+lbm_status lbm_step_from(lbm_ctx* ctx, const void* d_src, void* d_dst, void* d_fields);
+
 /* Writes dL/dS_T for L = m^p(T) into d_adj, given the state d_state (lbm_state_bytes, as from
  * lbm_get_state) of level T. Stream-ordered. */
 lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const void* d_state, void* d_adj);

@@ -47,9 +47,11 @@ def forward_states(sim, steps, checkpoint):
 def adjoint_gradients(sim, steps, checkpoint, cps, final_state, keep_fields=True):
     """Reverse sweep with checkpoint-and-recompute; returns (dL/dtheta per node, dL/dxi, lambda_0).
 
-    Each segment is recomputed from its checkpoint with enqueue-only steps; with keep_fields the
-    recomputation also keeps every level's rho^N, n* and rho^m (lbm_step_fields), which the
-    adjoint steps then reuse instead of recomputing (same values bit for bit)."""
+    Each segment is recomputed from its checkpoint with enqueue-only steps between state buffers
+    (lbm_step_from): the checkpoint itself is level s0 and every later level is written straight
+    into a buffer of its own, so no state is copied. With keep_fields the recomputation also keeps
+    every level's rho^N, n* and rho^m, which the adjoint steps then reuse instead of recomputing
+    (same values bit for bit). Memory: `checkpoint` state buffers, plus as many field buffers."""
     dev = sim.device
     lam = sim.new_adjoint()
     lam2 = sim.new_adjoint()
@@ -57,24 +59,24 @@ def adjoint_gradients(sim, steps, checkpoint, cps, final_state, keep_fields=True
     gth = torch.zeros(sim.N, dtype=torch.float64, device=dev)
     gxi = torch.zeros(1, dtype=torch.float64, device=dev)
     fields = [sim.new_fields() for _ in range(checkpoint)] if keep_fields else None
+    # bufs[k] holds level s0 + k (k >= 1); bufs[0] takes the output of the segment's last step,
+    # which is only run for its fields
+    bufs = [sim.new_state() for _ in range(checkpoint)]
     sim.adjoint_seed(final_state, lam)
     starts = sorted(cps)
     for s0 in reversed(starts):
         s1 = min(s0 + checkpoint, steps)
-        sim.set_state(cps[s0], s0)
-        seg = [cps[s0]]
+        seg = [cps[s0]] + bufs[1:s1 - s0]
         for t in range(s0, s1):
-            if keep_fields:
-                sim.step_fields(fields[t - s0])  # S_t -> S_{t+1}, keeping the fields of level t
-            elif t < s1 - 1:
-                sim.advance(1)  # stream-ordered: no host round trip inside the segment
+            k = t - s0
             if t < s1 - 1:
-                seg.append(sim.get_state(sync=False))
+                sim.step_from(seg[k], seg[k + 1], fields[k] if keep_fields else None)
+            elif keep_fields:
+                sim.step_from(seg[k], bufs[0], fields[k])
         for t in range(s1 - 1, s0 - 1, -1):
             sim.adjoint_step(seg[t - s0], lam, lam2, scratch, gth, gxi,
                              fields=fields[t - s0] if keep_fields else None)
             lam, lam2 = lam2, lam
-        del seg
     torch.cuda.synchronize(dev)
     return gth, gxi[0], lam
 

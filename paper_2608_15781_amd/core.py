@@ -21,7 +21,7 @@ EXPORTED = ["lbm_version", "lbm_workspace_bytes", "lbm_state_bytes", "lbm_init",
             "lbm_populations", "lbm_geometry", "lbm_state_layout", "lbm_get_state", "lbm_set_state",
             "lbm_set_profiling", "lbm_kernel_times", "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step",
             "lbm_steps_done", "lbm_free", "lbm_last_error", "lbm_fields_bytes", "lbm_step_fields",
-            "lbm_adjoint_step_fields"]
+            "lbm_adjoint_step_fields", "lbm_step_from"]
 KERNELS = ("colour", "extrap", "normal", "collide")
 
 
@@ -68,6 +68,7 @@ def lib():
         L.lbm_step_async.argtypes = [vp, i32]
         L.lbm_fields_bytes.argtypes = [P(Params), P(sz)]
         L.lbm_step_fields.argtypes = [vp, vp]
+        L.lbm_step_from.argtypes = [vp, vp, vp, vp]
         L.lbm_adjoint_step_fields.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lbm_populations.argtypes = [vp, vp, vp, vp]
@@ -236,6 +237,23 @@ class Lbm:
         self._check(lib().lbm_geometry(self._h, info.data_ptr(), wet.data_ptr()), self._h)
         self.stream.synchronize()
         return info, wet.view(self.N, 4).t()
+
+    def new_state(self):
+        """An uninitialised state buffer (uint8 tensor of state_bytes) for step_from."""
+        with self.torch.cuda.stream(self.stream):
+            return self.torch.empty(self.state_bytes, dtype=self.torch.uint8, device=self.device)
+
+    def step_from(self, src, dst, fields=None):
+        """One enqueued step from the state in `src` into `dst` (state buffers, as from get_state or
+        new_state); keeps its level-t fields in `fields` if given. The context's own state and step
+        count do not change."""
+        self._need(src, self.state_bytes, "source state")
+        self._need(dst, self.state_bytes, "destination state")
+        fp = None
+        if fields is not None:
+            self._need(fields, self.fields_bytes(), "fields")
+            fp = fields.data_ptr()
+        self._check(lib().lbm_step_from(self._h, src.data_ptr(), dst.data_ptr(), fp), self._h)
 
     def get_state(self, sync=True):
         """A copy of the state (uint8 tensor of state_bytes). With sync=False the copy is only

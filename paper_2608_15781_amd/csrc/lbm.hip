@@ -411,29 +411,21 @@ StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
   return A;
 }
 
+// The step's level-t fields (rho^N, n* with |G|, rho^m) go to a caller's buffer.
 template <int P>
-lbm_status launch_step(lbm_ctx* c, int slot, bool timed = true, void* fields = nullptr) {
+void use_fields(lbm_ctx* c, StepArgs<P>& A, void* fields) {
   using R = typename Prec<P>::R;
-  StepArgs<P> A = make_args<P>(c, c->cur);
-  if (fields) {  // this step's rho^N, n*, |G| and rho^m go to the caller's buffer
-    const FieldLayout FL = make_field_layout(c->p);
-    char* fb = static_cast<char*>(fields);
-    A.rhoN = reinterpret_cast<R*>(fb + FL.rhoN);
-    A.nst = reinterpret_cast<R*>(fb + FL.nst);
-    A.rm_out = reinterpret_cast<R*>(fb + FL.rm);
-  }
-  double* ring = reinterpret_cast<double*>(c->ws + c->L.ring);
-  A.ring_row = ring + 5 * size_t(slot);
-  // The previous step's partials are summed by k_normal of this step (its workgroup 0); the
-  // last step of a chunk is summed by launch_finish.
-  A.red_in = A.partials;
-  A.red_n = c->nb_fluid;
-  A.red_out = slot > 0 ? ring + 5 * size_t(slot - 1) : nullptr;
-  if (A.red_out && !c->nb_fluid)
-    hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlock), 0, c->stream, A.partials, c->nb_fluid, A.red_out);
-  const dim3 grid(c->L.nblocks), block(kBlock);
-  const dim3 gf(c->nb_fluid), ge(c->nb_ext);
-  hipEvent_t* ev = (c->prof && timed) ? &c->ev[5 * size_t(slot)] : nullptr;
+  const FieldLayout FL = make_field_layout(c->p);
+  char* fb = static_cast<char*>(fields);
+  A.rhoN = reinterpret_cast<R*>(fb + FL.rhoN);
+  A.nst = reinterpret_cast<R*>(fb + FL.nst);
+  A.rm_out = reinterpret_cast<R*>(fb + FL.rm);
+}
+
+// The four kernels of one step, with optional events (5) around them.
+template <int P>
+lbm_status enqueue_step(lbm_ctx* c, const StepArgs<P>& A, hipEvent_t* ev) {
+  const dim3 block(kBlock), gf(c->nb_fluid), ge(c->nb_ext);
   if (ev) HIP_TRY(c, hipEventRecord(ev[0], c->stream));
   if (c->nb_fluid) hipLaunchKernelGGL(k_colour<P>, gf, block, 0, c->stream, A);
   if (ev) HIP_TRY(c, hipEventRecord(ev[1], c->stream));
@@ -444,9 +436,51 @@ lbm_status launch_step(lbm_ctx* c, int slot, bool timed = true, void* fields = n
   if (c->nb_fluid) hipLaunchKernelGGL((k_collide<P, false>), gf, block, 0, c->stream, A);
   if (ev) HIP_TRY(c, hipEventRecord(ev[4], c->stream));
   HIP_TRY(c, hipGetLastError());
+  return LBM_OK;
+}
+
+template <int P>
+lbm_status launch_step(lbm_ctx* c, int slot, bool timed = true, void* fields = nullptr) {
+  StepArgs<P> A = make_args<P>(c, c->cur);
+  if (fields) use_fields<P>(c, A, fields);
+  double* ring = reinterpret_cast<double*>(c->ws + c->L.ring);
+  A.ring_row = ring + 5 * size_t(slot);
+  // The previous step's partials are summed by k_normal of this step (its workgroup 0); the
+  // last step of a chunk is summed by launch_finish.
+  A.red_in = A.partials;
+  A.red_n = c->nb_fluid;
+  A.red_out = slot > 0 ? ring + 5 * size_t(slot - 1) : nullptr;
+  if (A.red_out && !c->nb_fluid)
+    hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlock), 0, c->stream, A.partials, c->nb_fluid, A.red_out);
+  hipEvent_t* ev = (c->prof && timed) ? &c->ev[5 * size_t(slot)] : nullptr;
+  const lbm_status s = enqueue_step<P>(c, A, ev);
+  if (s != LBM_OK) return s;
   c->cur = 1 - c->cur;
   c->steps++;
   return LBM_OK;
+}
+
+// One step from a caller's state buffer into another; the context's state is not touched. The
+// per-block partial sums are written to the workspace as in every step and never reduced.
+template <int P>
+lbm_status launch_step_from(lbm_ctx* c, const void* src, void* dst, void* fields) {
+  using S = typename Prec<P>::S;
+  using R = typename Prec<P>::R;
+  StepArgs<P> A = make_args<P>(c, c->cur);
+  const char* sb = static_cast<const char*>(src);
+  char* db = static_cast<char*>(dst);
+  A.fin = reinterpret_cast<const S*>(sb + c->L.f_off);
+  A.ain = reinterpret_cast<const R*>(sb + c->L.a_off);
+  A.gin = reinterpret_cast<const S*>(sb + c->L.g_off);
+  A.fout = reinterpret_cast<S*>(db + c->L.f_off);
+  A.aout = reinterpret_cast<R*>(db + c->L.a_off);
+  A.gout = reinterpret_cast<S*>(db + c->L.g_off);
+  if (fields) use_fields<P>(c, A, fields);
+  A.ring_row = reinterpret_cast<double*>(c->ws + c->L.ring);
+  A.red_in = A.partials;
+  A.red_n = c->nb_fluid;
+  A.red_out = nullptr;
+  return enqueue_step<P>(c, A, nullptr);
 }
 
 // Final reduction of the last step of a chunk (ring row `slot`).
@@ -569,13 +603,8 @@ lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* fields, co
   char* sc = static_cast<char*>(scratch);
   StepArgs<P> A = make_args_from<P>(c, state);
   A.rm_out = reinterpret_cast<R*>(sc + AL.rmv);
-  if (fields) {  // level-t fields kept by the forward step: no recomputation
-    const FieldLayout FL = make_field_layout(c->p);
-    char* fb = const_cast<char*>(static_cast<const char*>(fields));
-    A.rhoN = reinterpret_cast<R*>(fb + FL.rhoN);
-    A.nst = reinterpret_cast<R*>(fb + FL.nst);
-    A.rm_out = reinterpret_cast<R*>(fb + FL.rm);
-  }
+  if (fields)  // level-t fields kept by the forward step: no recomputation
+    use_fields<P>(c, A, const_cast<void*>(fields));
   AdjArgs<R> J;
   J.lin = static_cast<const R*>(lin);
   J.lout = static_cast<R*>(lout);
@@ -820,6 +849,22 @@ lbm_status lbm_step_fields(lbm_ctx* c, void* d_fields) {
     case LBM_FP16_DEV: return launch_step<2>(c, 0, false, d_fields);
     default: return launch_step<3>(c, 0, false, d_fields);
   }
+}
+
+lbm_status lbm_step_from(lbm_ctx* c, const void* d_src, void* d_dst, void* d_fields) {
+  if (!c) return LBM_ERR_ARG;
+  if (!d_src || !d_dst) return fail(c, LBM_ERR_ARG, "source and destination states are required");
+  const char* s0 = static_cast<const char*>(d_src);
+  const char* d0 = static_cast<const char*>(d_dst);
+  const size_t nb = c->L.state_bytes;
+  if (s0 < d0 + nb && d0 < s0 + nb) return fail(c, LBM_ERR_ARG, "source and destination states overlap");
+  if (d_fields) {
+    const char* f0 = static_cast<const char*>(d_fields);
+    const size_t fb = make_field_layout(c->p).total;
+    if ((f0 < d0 + nb && d0 < f0 + fb) || (f0 < s0 + nb && s0 < f0 + fb))
+      return fail(c, LBM_ERR_ARG, "the fields buffer overlaps a state");
+  }
+  DISPATCH(c, launch_step_from, d_src, d_dst, d_fields);
 }
 
 lbm_status lbm_moments(lbm_ctx* c, void* rr, void* rp, void* rn, void* u, void* cc) {

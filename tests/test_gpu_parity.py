@@ -258,6 +258,45 @@ def test_checkpoint_roundtrip_and_determinism(core, oracle_mod):
     assert np.array_equal(a.get_state().cpu().numpy(), c.get_state(sync=False).cpu().numpy())
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp16"])
+def test_step_between_buffers(core, precision):
+    """lbm_step_from: steps between caller buffers are bitwise those of lbm_step, keep the same
+    fields as lbm_step_fields and leave the context's own state alone; aliased buffers are refused."""
+    shape = (19, 13, 11)
+    solid, theta, rr0, rp0 = _full_case(shape, seed=29)
+    kw = dict(FULL_KW)
+    kw["tau_species"] = kw.pop("tau_c")
+    a = core.Lbm(shape, solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision=precision, **kw)
+    a.step(9)
+    s0 = a.get_state()
+    own = s0.clone()
+    bufs = [a.new_state().zero_() for _ in range(3)]  # padding past the fluid nodes: zero, as in the context
+    fa, fb = a.new_fields().zero_(), a.new_fields().zero_()  # entries no step writes compare equal
+    a.step_from(s0, bufs[0], fa)
+    a.step_from(bufs[0], bufs[1])
+    a.step_from(bufs[1], bufs[2])
+    assert a.steps_done == 9
+    assert np.array_equal(a.get_state().cpu().numpy(), own.cpu().numpy())
+    a.step_fields(fb)  # level 9 -> 10 on the context's state
+    a.step(2)
+    assert np.array_equal(fa.cpu().numpy(), fb.cpu().numpy())
+    assert np.array_equal(a.get_state().cpu().numpy(), bufs[2].cpu().numpy())
+    with pytest.raises(core.LbmError) as e:
+        a.step_from(bufs[0], bufs[0])
+    assert e.value.status == core.LBM_ERR_ARG
+    # partial overlaps (refused on the host, before any launch)
+    import torch
+
+    sb, fbytes = a.state_bytes, a.fields_bytes()
+    big = torch.zeros(2 * sb + fbytes + 256, dtype=torch.uint8, device=s0.device)
+    with pytest.raises(core.LbmError) as e:
+        a.step_from(big[:sb], big[256:256 + sb])
+    assert e.value.status == core.LBM_ERR_ARG
+    with pytest.raises(core.LbmError) as e:  # fields buffer overlapping the destination's tail
+        a.step_from(big[:sb], big[sb + 256:2 * sb + 256], big[2 * sb:2 * sb + fbytes])
+    assert e.value.status == core.LBM_ERR_ARG
+
+
 def test_nonfinite_is_reported(core):
     """A NaN planted in the state through set_state makes lbm_step return LBM_ERR_NONFINITE."""
     import torch
