@@ -182,9 +182,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(StepArgs<P> A, typename Pre
 
 // ---------------------------------------------------------------------------------------------
 // Reverse of the collide kernel at one fluid node (forward arithmetic recomputed as in k_collide).
+// Register budget: the pull sources and the species populations, needed again only at the end,
+// wait in LDS (25 KB per workgroup in FP32), which brings the FP32/FP16/BF16 kernels to 165
+// VGPRs and three waves per SIMD (requested below) without spills; FP64 keeps one wave.
 // ---------------------------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
+__global__ __launch_bounds__(kBlock, P == 0 ? 1 : 3) void k_adj_collide(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
   const int t = logical_block() * kBlock + threadIdx.x;
@@ -195,9 +198,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     const Nbr nb = make_nbr(n, A.geo);
     const size_t N = A.N;
     // ---------------- forward recompute ----------------
+    // The pull sources are needed again by the final scatter; they wait in LDS meanwhile.
+    __shared__ int sid_lds[18][kBlock];
     int sid[18];
 #pragma unroll
-    for (int i = 0; i < 18; ++i) sid[i] = ((inf >> i) & 1u) ? t : A.fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
+    for (int i = 0; i < 18; ++i) {
+      sid[i] = ((inf >> i) & 1u) ? t : A.fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
+      sid_lds[i][threadIdx.x] = sid[i];
+    }
     R f[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
@@ -228,8 +236,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     const R glen = nsv.w;
     const bool has_n = glen > A.eps;
     R H = 0;
-    R Jm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    R Js[3] = {0, 0, 0};  // sum_b n*_b (J_ab + J_ba), the only part of J the reverse needs
     if (has_n) {
+      R Jm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
       for (int i = 0; i < 18; ++i) {
         const typename V4<R>::T mv = ld4(A.nst, sid[D::opp[i]]);  // own id where x + c_i is solid
@@ -245,6 +254,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
 #pragma unroll
         for (int b = 0; b < 3; ++b) nJn += nn[a] * nn[b] * Jm[a][b];
       H = -((Jm[0][0] + Jm[1][1] + Jm[2][2]) - nJn);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        R s = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) s += nn[b] * (Jm[a][b] + Jm[b][a]);
+        Js[a] = s;
+      }
     }
     const R fc = R(0.5) * A.sigma * H * glen * irm;
     R dur[3], dup[3];
@@ -252,6 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     for (int a = 0; a < 3; ++a) { dur[a] = fc * nn[a] + A.acc[0][a]; dup[a] = fc * nn[a] + A.acc[1][a]; }
     const R up[3] = {ux + R(0.5) * (rr * dur[0] + rp * dup[0]) * irm, uy + R(0.5) * (rr * dur[1] + rp * dup[1]) * irm,
                      uz + R(0.5) * (rr * dur[2] + rp * dup[2]) * irm};
+    __shared__ R g_lds[7][kBlock];
     R g[7] = {0, 0, 0, 0, 0, 0, 0};
     R C = R(1);
     const bool inlet = A.species && (inf & kInlet);
@@ -271,6 +288,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
       C = 0;
 #pragma unroll
       for (int i = 0; i < 7; ++i) C += g[i];
+#pragma unroll
+      for (int i = 0; i < 7; ++i) g_lds[i][threadIdx.x] = g[i];
       if (inlet) C = A.c_in;
     }
     const R Ur[3] = {ux + dur[0], uy + dur[1], uz + dur[2]};
@@ -305,6 +324,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     R l_C = 0, l_delta = 0, l_up[3] = {0, 0, 0};
     R l_g[7] = {0, 0, 0, 0, 0, 0, 0};
     if (A.species) {
+      asm volatile("" ::: "memory");  // read LDS back: no store-to-load forwarding into registers
+#pragma unroll
+      for (int i = 0; i < 7; ++i) g[i] = g_lds[i][threadIdx.x];
       const R sink = reacts ? R(1) - delta / C : R(1);
       R l_sink = 0;
 #pragma unroll
@@ -439,12 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
     if (has_n) {
       // H = -(tr J - n.J.n): dependence on the centre normal, including solid neighbours' copies.
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        R s = 0;
-#pragma unroll
-        for (int b = 0; b < 3; ++b) s += nn[b] * (Jm[a][b] + Jm[b][a]);
-        l_n[a] += l_H * s;
-      }
+      for (int a = 0; a < 3; ++a) l_n[a] += l_H * Js[a];
 #pragma unroll
       for (int i = 0; i < 18; ++i) {
         if ((inf >> D::opp[i]) & 1u) {
@@ -468,6 +485,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(StepArgs<P> A, AdjArgs<t
 #pragma unroll
       for (int i = 0; i < 7; ++i) l_g[i] += l_C;
     // pulled populations: rm = sum f, m = sum f c, second moments
+    asm volatile("" ::: "memory");  // read LDS back: no store-to-load forwarding into registers
+#pragma unroll
+    for (int i = 0; i < 18; ++i) sid[i] = sid_lds[i][threadIdx.x];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
       const int cx = D::cx[i], cy = D::cy[i], cz = D::cz[i];
@@ -529,19 +549,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
   R mu[3] = {J.lnc[n], J.lnc[N + n], J.lnc[2 * N + n]};
   // H(x) at each fluid neighbour x = y - c_i used n*(x + c_i) = n*(y):
   // dH(x)/dn*_a(y) = -3 w_i (c_ia - n_a(x) (n(x).c_i)).
+  // Loads first, in two dependent rounds for all directions at once (dH/d and fluid id, then the
+  // normal); a solid y - c_i reads this node's own entries and is discarded.
+  R lh[18];
+  int mid[18];
 #pragma unroll
   for (int i = 0; i < 18; ++i) {
-    if ((inf >> i) & 1u) continue;  // y - c_i is solid
-    const int m = nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
-    const R lh = J.lH[m];
-    if (lh == R(0)) continue;
-    const typename V4<R>::T qv = ld4(A.nst, A.fid[m]);
+    const int m = ((inf >> i) & 1u) ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+    lh[i] = J.lH[m];
+    mid[i] = A.fid[m];
+  }
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    const typename V4<R>::T qv = ld4(A.nst, mid[i]);
+    const bool use = !((inf >> i) & 1u) && lh[i] != R(0);
     const R q0 = qv.x, q1 = qv.y, q2 = qv.z;
     const R cn = R(D::cx[i]) * q0 + R(D::cy[i]) * q1 + R(D::cz[i]) * q2;
-    const R w3 = R(-3.0 * D::w(i)) * lh;
-    mu[0] += w3 * (R(D::cx[i]) - q0 * cn);
-    mu[1] += w3 * (R(D::cy[i]) - q1 * cn);
-    mu[2] += w3 * (R(D::cz[i]) - q2 * cn);
+    const R w3 = R(-3.0 * D::w(i)) * lh[i];
+    mu[0] = use ? mu[0] + w3 * (R(D::cx[i]) - q0 * cn) : mu[0];
+    mu[1] = use ? mu[1] + w3 * (R(D::cy[i]) - q1 * cn) : mu[1];
+    mu[2] = use ? mu[2] + w3 * (R(D::cz[i]) - q2 * cn) : mu[2];
   }
   // Recompute the raw gradient and the normal of this node (as k_normal).
   R g[3] = {0, 0, 0};
@@ -608,18 +635,27 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(StepArgs<P> A, AdjArgs<type
   const uint32_t inf = EXT ? A.einfo[t] : A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
-  R s = 0;
+  // Every load is issued before any is used; a direction whose source is solid reads this
+  // node's own entries and is discarded.
+  R gx[18], gy[18], gz[18];
 #pragma unroll
   for (int i = 0; i < 18; ++i) {
     // fluid y: bit i set means y - c_i is solid; solid y: bit opp(i) set means y - c_i is fluid
     const bool src_fluid = EXT ? ((inf >> D::opp[i]) & 1u) : !((inf >> i) & 1u);
-    if (!src_fluid) continue;
-    const int m = nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
+    const int m = src_fluid ? nb.at(-D::cx[i], -D::cy[i], -D::cz[i]) : n;
+    gx[i] = D::cx[i] ? J.lG[m] : R(0);
+    gy[i] = D::cy[i] ? J.lG[N + m] : R(0);
+    gz[i] = D::cz[i] ? J.lG[2 * N + m] : R(0);
+  }
+  R s = 0;
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    const bool src_fluid = EXT ? ((inf >> D::opp[i]) & 1u) : !((inf >> i) & 1u);
     R v = 0;
-    if (D::cx[i]) v += R(D::cx[i]) * J.lG[m];
-    if (D::cy[i]) v += R(D::cy[i]) * J.lG[N + m];
-    if (D::cz[i]) v += R(D::cz[i]) * J.lG[2 * N + m];
-    s += R(3.0 * D::w(i)) * v;
+    if (D::cx[i]) v += R(D::cx[i]) * gx[i];
+    if (D::cy[i]) v += R(D::cy[i]) * gy[i];
+    if (D::cz[i]) v += R(D::cz[i]) * gz[i];
+    s = src_fluid ? s + R(3.0 * D::w(i)) * v : s;
   }
   J.lrn[n] = EXT ? s : J.lrn[n] + s;
 }
@@ -638,17 +674,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_colour(StepArgs<P> A, AdjArgs<ty
   const int n = A.fluid[t];
   const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
+  // Loads for all directions first (a fluid z - c_j reads this node's own entries, discarded).
+  uint32_t iy[18];
+  R ly[18];
+#pragma unroll
+  for (int j = 0; j < 18; ++j) {
+    const int y = ((inf >> j) & 1u) ? nb.at(-D::cx[j], -D::cy[j], -D::cz[j]) : n;
+    iy[j] = A.info[y];
+    ly[j] = J.lrn[y];
+  }
   R l = J.lrn[n];
 #pragma unroll
   for (int j = 0; j < 18; ++j) {
     if (!((inf >> j) & 1u)) continue;  // z - c_j is fluid
-    const int y = nb.at(-D::cx[j], -D::cy[j], -D::cz[j]);
-    const uint32_t iy = A.info[y];
     R den = 0;
 #pragma unroll
     for (int k = 0; k < 18; ++k)
-      if ((iy >> k) & 1u) den += R(D::w(k));
-    l += R(D::w(j)) / den * J.lrn[y];
+      if ((iy[j] >> k) & 1u) den += R(D::w(k));
+    l += R(D::w(j)) / den * ly[j];
   }
   const R rm = J.rmv[n];
   const R q = A.rhoN[n];

@@ -294,17 +294,20 @@ __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs<P> A) {
   const int n = A.ext[t];
   const uint32_t inf = A.einfo[t];
   const Nbr nb = make_nbr(n, A.geo);
+  // All 18 loads are issued before any is used (a direction without a fluid neighbour reads the
+  // node's own entry and discards it), so their latencies overlap.
+  R qv[18];
+#pragma unroll
+  for (int i = 0; i < 18; ++i) qv[i] = A.rhoN[((inf >> i) & 1u) ? nb.at(D::cx[i], D::cy[i], D::cz[i]) : n];
   // Weighted sums of the offsets q and of the sides s separately; -0 as the start keeps the
   // sign of an all-(-0) sum.
   R nq = R(-0.0), ns = 0, den = 0;
 #pragma unroll
   for (int i = 0; i < 18; ++i) {
-    if ((inf >> i) & 1u) {
-      const R q = A.rhoN[nb.at(D::cx[i], D::cy[i], D::cz[i])];
-      nq += R(D::w(i)) * q;
-      ns += R(D::w(i)) * rn_side(q);
-      den += R(D::w(i));
-    }
+    const bool use = (inf >> i) & 1u;
+    nq = use ? nq + R(D::w(i)) * qv[i] : nq;
+    ns = use ? ns + R(D::w(i)) * rn_side(qv[i]) : ns;
+    den = use ? den + R(D::w(i)) : den;
   }
   if (ns == den || ns == -den) {
     A.rhoN[n] = nq / den;  // all neighbours on one side: the average keeps that side
