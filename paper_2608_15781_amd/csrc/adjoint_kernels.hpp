@@ -622,8 +622,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
 
 // ---------------------------------------------------------------------------------------------
 // Transpose of G(x) = 3 sum_i w_i c_i rho^N(x + c_i): d/d rho^N(y) gathers 3 w_i c_i . lG(y - c_i)
-// over fluid nodes y - c_i. EXT: y is a solid node with extrapolated colour (otherwise fluid, and
-// the collide part of d/d rho^N is added).
+// over fluid nodes y - c_i. EXT: y is a solid node with extrapolated colour, and what is stored is
+// d/d rho^N(y) / den(y), den(y) = sum of w_k over the fluid nodes y + c_k (the extrapolation's
+// weight sum, the only form in which its transpose uses it); otherwise y is fluid and the collide
+// part of d/d rho^N is added.
 // ---------------------------------------------------------------------------------------------
 template <int P, bool EXT>
 __global__ __launch_bounds__(kBlock) void k_adj_grad(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
@@ -657,7 +659,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(StepArgs<P> A, AdjArgs<type
     if (D::cz[i]) v += R(D::cz[i]) * gz[i];
     s = src_fluid ? s + R(3.0 * D::w(i)) * v : s;
   }
-  J.lrn[n] = EXT ? s : J.lrn[n] + s;
+  if (EXT) {
+    R den = 0;  // > 0: a solid node on this list has a fluid neighbour
+#pragma unroll
+    for (int k = 0; k < 18; ++k) den = ((inf >> k) & 1u) ? den + R(D::w(k)) : den;
+    J.lrn[n] = s / den;
+  } else {
+    J.lrn[n] += s;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -674,25 +683,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_colour(StepArgs<P> A, AdjArgs<ty
   const int n = A.fluid[t];
   const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
-  // Loads for all directions first (a fluid z - c_j reads this node's own entries, discarded).
-  uint32_t iy[18];
+  // At a solid y the adjoint is stored already divided by den(y) (k_adj_grad). Loads for all
+  // directions first (a fluid z - c_j reads this node's own entry, discarded).
   R ly[18];
 #pragma unroll
-  for (int j = 0; j < 18; ++j) {
-    const int y = ((inf >> j) & 1u) ? nb.at(-D::cx[j], -D::cy[j], -D::cz[j]) : n;
-    iy[j] = A.info[y];
-    ly[j] = J.lrn[y];
-  }
+  for (int j = 0; j < 18; ++j) ly[j] = J.lrn[((inf >> j) & 1u) ? nb.at(-D::cx[j], -D::cy[j], -D::cz[j]) : n];
   R l = J.lrn[n];
 #pragma unroll
-  for (int j = 0; j < 18; ++j) {
-    if (!((inf >> j) & 1u)) continue;  // z - c_j is fluid
-    R den = 0;
-#pragma unroll
-    for (int k = 0; k < 18; ++k)
-      if ((iy[j] >> k) & 1u) den += R(D::w(k));
-    l += R(D::w(j)) / den * ly[j];
-  }
+  for (int j = 0; j < 18; ++j) l = ((inf >> j) & 1u) ? l + R(D::w(j)) * ly[j] : l;  // z - c_j is solid
   const R rm = J.rmv[n];
   const R q = A.rhoN[n];
   const R one_plus_rn = signbit(q) ? R(2) + q : q;  // 1 + rho^N = 2 rho^r / rho^m
