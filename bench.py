@@ -127,6 +127,36 @@ def rel_l2(a, b):
     return float(((a - b).norm() / b.norm()).item()) if b.norm() > 0 else float((a - b).norm().item())
 
 
+def device_copy_gbs(torch, nbytes=1 << 30, reps=10):
+    """Achievable streaming rate: bytes read + written per second by a device-to-device copy of a
+    buffer four times the last-level cache, timed with events on the current stream."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / sec / 1e9
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, solid, theta, rr0, rp0, nfluid, steps):
     import oracle
 
@@ -137,7 +167,8 @@ def cpu_baseline(w, solid, theta, rr0, rp0, nfluid, steps):
     o.step(steps)
     dt = time.perf_counter() - t0
     return dict(value=nfluid * steps / dt / 1e6, unit="MFLUPS", cores=oracle.get_threads(), kind="oracle",
-                sample="%d steps of the full 128^3 workload (FP64, OpenMP over z), %.1f s" % (steps, dt))
+                sample="%d steps of the full 128^3 workload (FP64, OpenMP over z), %.1f s" % (steps, dt),
+                cpu_model=cpu_model())
 
 
 def main():
@@ -226,6 +257,7 @@ def main():
         cpu = cpu_baseline(w, solid, theta, rr0, rp0, nfluid, args.cpu_steps)
 
     traffic = measured_traffic("fp32", "lbm::k_collide<1, false>")
+    copy_gbs = device_copy_gbs(torch)
 
     out = {
         "metric": METRIC,
@@ -246,7 +278,8 @@ def main():
         "mlups_all_nodes": round(nall * args.steps / dt32 / 1e6, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_collide",
-                     "alg_bytes_per_fluid_node": b["collide"], "avg_launch_ms": round(kern32["collide"], 5)},
+                     "alg_bytes_per_fluid_node": b["collide"], "avg_launch_ms": round(kern32["collide"], 5),
+                     "device_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "step_roofline": {"alg_bytes_per_fluid_update": b["step_min"],
                           "frac": round(mflups * 1e6 * b["step_min"] / (HBM_PEAK_GBS * 1e9), 4),
                           "naive45_bytes_per_fluid_update": b["naive45"],
