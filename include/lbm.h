@@ -72,7 +72,11 @@ typedef struct {
   double c_inlet;          /* species inlet concentration (x_open) */
   double grad_eps;         /* colour gradients with |grad rho^N| <= grad_eps give n = 0; > 0 */
   int32_t fp16_scale_log2; /* deviation scale exponent for LBM_FP16_DEV, 0..20 */
-  int32_t reserved;        /* must be 0 */
+  int32_t fluid_nodes;     /* number of fluid nodes of the mask, which sizes the state and adjoint
+                            * planes and the per-fluid-node arrays (half the memory of an every-node
+                            * layout at porosity 0.5); 0 sizes them for every node. Every size query
+                            * and lbm_init must see the same value; lbm_init rejects a mask whose
+                            * fluid count differs. 0..nx*ny*nz */
 } lbm_params;
 
 /* Level-t sums of one step (eqs. reactant_mass, product_mass, production_rate), in FP64:
@@ -104,7 +108,8 @@ lbm_status lbm_state_bytes(const lbm_params* params, size_t* bytes);
  * caller and used by the context until lbm_free. stream: hipStream_t or NULL (default stream).
  * Errors: LBM_ERR_ARG for invalid parameters or inputs (tau <= 0.5, negative sigma/beta/xi,
  * theta outside [0, pi], non-finite values, non-positive mixture density at a fluid node,
- * misaligned or too small workspace); LBM_ERR_HIP. *out is set only on success. */
+ * misaligned or too small workspace, params->fluid_nodes > 0 differing from the mask's fluid
+ * count); LBM_ERR_HIP. *out is set only on success. */
 lbm_status lbm_init(const lbm_params* params, const uint8_t* solid, const double* theta, double theta_uniform,
                     const uint8_t* reactive, const double* rho_r0, const double* rho_p0, const double* c0,
                     void* d_workspace, size_t workspace_bytes, void* stream, lbm_ctx** out);
@@ -143,7 +148,8 @@ lbm_status lbm_populations(lbm_ctx* ctx, void* d_fr, void* d_fp, void* d_g);
 lbm_status lbm_geometry(lbm_ctx* ctx, void* d_info, void* d_wet);
 
 /* Byte offsets inside a state snapshot of its three parts, and the plane stride P (elements;
- * P >= N, padded so that planes are an odd multiple of 256 bytes apart): the 19 colour-blind
+ * P >= F, F = params->fluid_nodes, or N when that is 0, padded so that planes are an odd multiple
+ * of 256 bytes apart): the 19 colour-blind
  * population planes f^m (storage type, population-major [i*P + f]), the colour scalars as one
  * 4-vector per node (e, v_x, v_y, v_z; real type, [4*f + k]) and the 7 species planes (storage
  * type, [i*P + f]; absent without species). The per-colour populations are

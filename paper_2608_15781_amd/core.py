@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("tau_species", ctypes.c_double), ("sigma", ctypes.c_double),
         ("beta", ctypes.c_double), ("xi", ctypes.c_double), ("accel", (ctypes.c_double * 3) * 2),
         ("c_inlet", ctypes.c_double), ("grad_eps", ctypes.c_double), ("fp16_scale_log2", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("fluid_nodes", ctypes.c_int32),
     ]
 
 
@@ -95,7 +95,7 @@ def lib():
 
 def make_params(shape, precision="fp32", tau=1.0, tau_species=0.9, sigma=0.0, beta=0.7, xi=0.0,
                 accel=((0, 0, 0), (0, 0, 0)), species=False, x_open=False, c_inlet=1.0, grad_eps=1e-6,
-                fp16_scale_log2=12) -> Params:
+                fp16_scale_log2=12, fluid_nodes=0) -> Params:
     p = Params()
     p.nx, p.ny, p.nz = (int(s) for s in shape)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -104,7 +104,8 @@ def make_params(shape, precision="fp32", tau=1.0, tau_species=0.9, sigma=0.0, be
     for k in range(2):
         for a in range(3):
             p.accel[k][a] = float(accel[k][a])
-    p.c_inlet, p.grad_eps, p.fp16_scale_log2, p.reserved = c_inlet, grad_eps, fp16_scale_log2, 0
+    p.c_inlet, p.grad_eps, p.fp16_scale_log2 = c_inlet, grad_eps, fp16_scale_log2
+    p.fluid_nodes = int(fluid_nodes)
     return p
 
 
@@ -127,11 +128,13 @@ class Lbm:
     """One simulation context on one GPU.
 
     shape = (nx, ny, nz); per-node inputs are arrays of shape (nz, ny, nx) (x fastest) or flat.
-    Keyword parameters map one to one onto lbm_params (see include/lbm.h).
+    Keyword parameters map one to one onto lbm_params (see include/lbm.h). compact=True sizes the
+    state, adjoint and per-fluid-node buffers for the mask's fluid nodes (lbm_params.fluid_nodes);
+    False sizes them for every node.
     """
 
     def __init__(self, shape, solid=None, theta=None, theta_uniform=math.pi / 2, reactive=None, rho_r0=1.0,
-                 rho_p0=0.0, c0=None, device="cuda:0", stream=None, **kw):
+                 rho_p0=0.0, c0=None, device="cuda:0", stream=None, compact=True, **kw):
         import torch
 
         self.torch = torch
@@ -144,6 +147,12 @@ class Lbm:
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         L = lib()
+        N = self.N
+        solid = np.zeros(N, np.uint8) if solid is None else _host(solid, np.uint8, N)
+        self.solid = solid
+        self.nfluid = int((solid == 0).sum())  # state entries, fluid nodes in node order
+        # compact: state and per-fluid-node arrays sized for the mask's fluid nodes (else for every node)
+        self.params.fluid_nodes = self.nfluid if compact else 0
         ws = ctypes.c_size_t()
         self._check(L.lbm_workspace_bytes(ctypes.byref(self.params), ctypes.byref(ws)), None)
         sb = ctypes.c_size_t()
@@ -153,14 +162,10 @@ class Lbm:
         base = self.workspace.data_ptr()
         off = (-base) % 256
         self._ws_ptr = base + off
-        N = self.N
-        solid = np.zeros(N, np.uint8) if solid is None else _host(solid, np.uint8, N)
         th = _host(theta, np.float64, N)
         react = _host(reactive, np.uint8, N)
         rr, rp = _host(rho_r0, np.float64, N), _host(rho_p0, np.float64, N)
         c0a = _host(c0, np.float64, N)
-        self.solid = solid
-        self.nfluid = int((solid == 0).sum())  # state entries, fluid nodes in node order
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = L.lbm_init(ctypes.byref(self.params), _p(solid), _p(th), float(theta_uniform), _p(react), _p(rr),

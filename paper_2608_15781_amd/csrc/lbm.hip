@@ -3,6 +3,7 @@
 // step_kernels.hpp. Build: hipcc --offload-arch=gfx950 (see the package's build module).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -35,13 +36,29 @@ struct Layout {
   int nblocks;  // one thread per node, rounded up to a multiple of kXcd workgroups
 };
 
-// Plane stride: at least N elements and an odd multiple of 256 bytes of storage, so that the
-// same entry of different planes does not fall on one memory channel (N = 2^k would put every
-// plane 2^k elements apart).
-size_t plane_stride(const lbm_params& p) {
+// Upper bounds of the two launch lists: the fluid nodes (params.fluid_nodes when given, else
+// every node) and the solid nodes next to fluid (at most the solid nodes).
+size_t fluid_bound(const lbm_params& p) {
   const size_t N = size_t(p.nx) * p.ny * p.nz;
+  return p.fluid_nodes > 0 ? size_t(p.fluid_nodes) : N;
+}
+size_t ext_bound(const lbm_params& p) {
+  const size_t N = size_t(p.nx) * p.ny * p.nz;
+  return p.fluid_nodes > 0 ? N - size_t(p.fluid_nodes) : N;
+}
+
+// Bytes of host inputs staged on the device during lbm_init: theta, rho_r0, rho_p0, c0 (doubles)
+// and the solid and reactive masks (bytes), N each.
+size_t stage_bytes(const lbm_params& p) { return 34 * size_t(p.nx) * p.ny * p.nz; }
+
+// Plane stride of the state and adjoint planes, which are indexed by fluid id: at least the
+// number of fluid nodes and an odd multiple of 256 bytes of storage, so that the same entry of
+// different planes does not fall on one memory channel (a power-of-two count would put every
+// plane on the same one).
+size_t plane_stride(const lbm_params& p) {
+  const size_t F = fluid_bound(p);
   const size_t unit = 256 / store_bytes(p.precision);
-  size_t m = (N + unit - 1) / unit;
+  size_t m = (F + unit - 1) / unit;
   if (m % 2 == 0) ++m;
   return m * unit;
 }
@@ -49,6 +66,7 @@ size_t plane_stride(const lbm_params& p) {
 Layout make_layout(const lbm_params& p) {
   Layout L{};
   const size_t N = size_t(p.nx) * p.ny * p.nz;
+  const size_t F = fluid_bound(p), E = ext_bound(p);
   const size_t s = store_bytes(p.precision), r = real_bytes(p.precision);
   const size_t ps = plane_stride(p);
   L.ps = ps;
@@ -60,20 +78,22 @@ Layout make_layout(const lbm_params& p) {
   nb = (nb + kXcd - 1) / kXcd * kXcd;
   L.nblocks = nb;
   size_t o = 0;
-  L.info = o; o = align_up(o + 4 * N);
-  L.wet = o; o = align_up(o + 4 * r * N);
-  L.rhoN = o; o = align_up(o + r * N);
-  L.nst = o; o = align_up(o + 4 * r * N);
-  L.state[0] = o; o = align_up(o + L.state_bytes);
-  L.state[1] = o; o = align_up(o + L.state_bytes);
+  L.info = o; o = align_up(o + 4 * N);      // per node
+  L.wet = o; o = align_up(o + 4 * r * F);   // per fluid id
+  L.rhoN = o; o = align_up(o + r * N);      // per node (read at solid nodes too)
+  L.nst = o; o = align_up(o + 4 * r * F);   // per fluid id
   L.partials = o; o = align_up(o + 5 * sizeof(double) * size_t(nb));
   L.ring = o; o = align_up(o + 5 * sizeof(double) * kRing);
-  L.lists[0] = o; o = align_up(o + 4 * N);  // fluid nodes
-  L.lists[1] = o; o = align_up(o + 4 * N);  // solid nodes with extrapolated colour
-  L.linfo[0] = o; o = align_up(o + 4 * N);  // info words of the list entries
-  L.linfo[1] = o; o = align_up(o + 4 * N);
+  L.lists[0] = o; o = align_up(o + 4 * F);  // fluid nodes
+  L.lists[1] = o; o = align_up(o + 4 * E);  // solid nodes with extrapolated colour
+  L.linfo[0] = o; o = align_up(o + 4 * F);  // info words of the list entries
+  L.linfo[1] = o; o = align_up(o + 4 * E);
   L.fid = o; o = align_up(o + 4 * N);       // node -> fluid id
   L.counts = o; o = align_up(o + 4 * (size_t(nb) + 2));
+  L.state[0] = o; o = align_up(o + L.state_bytes);
+  // The second state buffer comes last: lbm_init stages the host inputs there and in whatever
+  // lies beyond it, so the workspace extends to the larger of the two.
+  L.state[1] = o; o = align_up(o + std::max(L.state_bytes, stage_bytes(p)));
   L.total = o;
   return L;
 }
@@ -95,7 +115,7 @@ FieldLayout make_field_layout(const lbm_params& p) {
   const size_t r = real_bytes(p.precision);
   size_t o = 0;
   F.rhoN = o; o = align_up(o + r * N);
-  F.nst = o; o = align_up(o + 4 * r * N);
+  F.nst = o; o = align_up(o + 4 * r * fluid_bound(p));
   F.rm = o; o = align_up(o + r * N);
   F.total = o;
   return F;
@@ -179,7 +199,10 @@ lbm_status check_params(const lbm_params* p, char* msg, size_t len) {
       if (!std::isfinite(p->accel[k][a])) { snprintf(msg, len, "accel must be finite"); return LBM_ERR_ARG; }
   if (p->species && p->x_open && (!std::isfinite(p->c_inlet) || p->c_inlet < 0)) { snprintf(msg, len, "c_inlet must be finite and >= 0"); return LBM_ERR_ARG; }
   if (p->precision == LBM_FP16_DEV && (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 20)) { snprintf(msg, len, "fp16_scale_log2 must be in 0..20"); return LBM_ERR_ARG; }
-  if (p->reserved != 0) { snprintf(msg, len, "reserved must be 0"); return LBM_ERR_ARG; }
+  if (p->fluid_nodes < 0 || double(p->fluid_nodes) > N) {
+    snprintf(msg, len, "fluid_nodes must be in 0..nx*ny*nz");
+    return LBM_ERR_ARG;
+  }
   if (p->species != 0 && p->species != 1) { snprintf(msg, len, "species must be 0 or 1"); return LBM_ERR_ARG; }
   return LBM_OK;
 }
@@ -695,6 +718,14 @@ lbm_status lbm_init(const lbm_params* params, const uint8_t* solid, const double
   if (!theta && !(theta_uniform >= 0 && theta_uniform <= M_PI)) {
     snprintf(g_err, sizeof(g_err), "theta_uniform must be in [0, pi]");
     return LBM_ERR_ARG;
+  }
+  if (params->fluid_nodes > 0) {
+    size_t nf = 0;
+    for (size_t n = 0; n < N; ++n) nf += solid[n] ? 0 : 1;
+    if (nf != size_t(params->fluid_nodes)) {
+      snprintf(g_err, sizeof(g_err), "fluid_nodes = %d but the mask has %zu fluid nodes", params->fluid_nodes, nf);
+      return LBM_ERR_ARG;
+    }
   }
   for (size_t n = 0; n < N; ++n) {
     if (solid[n]) continue;

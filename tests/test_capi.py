@@ -74,13 +74,67 @@ def test_state_layout_and_plane_stride(core, prec, s, r, species):
 
 @pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("sigma", -1.0), ("beta", -0.1),
                                          ("xi", -1e-3), ("grad_eps", 0.0), ("nx", 0), ("precision", 7),
-                                         ("reserved", 1), ("fp16_scale_log2", 40)])
+                                         ("fluid_nodes", -1), ("fluid_nodes", 8 ** 3 + 1),
+                                         ("fp16_scale_log2", 40)])
 def test_invalid_params_rejected(core, field, value):
     p = core.make_params((8, 8, 8), precision="fp16", tau=0.8)
     setattr(p, field, value)
     b = ctypes.c_size_t()
     assert core.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == core.LBM_ERR_ARG
     assert core.lib().lbm_last_error(None)
+
+
+@pytest.mark.parametrize("prec,s,r", [("fp64", 8, 8), ("fp32", 4, 4), ("fp16", 2, 4), ("bf16", 2, 4)])
+def test_layout_sized_by_fluid_nodes(core, prec, s, r):
+    """With the mask's fluid count the planes hold that many entries (not one per node): the
+    state, adjoint and fields buffers shrink with the porosity, and the workspace still has room
+    for the 34 bytes per node that lbm_init stages."""
+    shape = (64, 48, 40)
+    N = 64 * 48 * 40
+
+    def sizes(nf):
+        p = core.make_params(shape, precision=prec, tau=0.8, species=True, fluid_nodes=nf)
+        out = [ctypes.c_size_t() for _ in range(6)]
+        assert core.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(out[0])) == 0
+        assert core.lib().lbm_state_bytes(ctypes.byref(p), ctypes.byref(out[1])) == 0
+        assert core.lib().lbm_adjoint_bytes(ctypes.byref(p), ctypes.byref(out[2]), ctypes.byref(out[3])) == 0
+        assert core.lib().lbm_fields_bytes(ctypes.byref(p), ctypes.byref(out[4])) == 0
+        f, a, g = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        assert core.lib().lbm_state_layout(ctypes.byref(p), ctypes.byref(f), ctypes.byref(a), ctypes.byref(g),
+                                           ctypes.byref(out[5])) == 0
+        return [o.value for o in out]
+
+    ws_all, sb_all, ab_all, _, fb_all, ps_all = sizes(0)
+    nf = N // 2 + 37
+    ws, sb, ab, scr, fb, ps = sizes(nf)
+    unit = 256 // s
+    assert nf <= ps < nf + 2 * unit and ps_all >= N
+    assert sb >= (26 * s + 4 * r) * ps and sb < 0.55 * sb_all
+    assert ab >= 30 * r * ps and ab < 0.55 * ab_all
+    assert fb < fb_all and ws < ws_all
+    assert ws >= 2 * sb
+    # a nearly solid lattice: the init staging, not the state, sets the size of the tail
+    ws1 = sizes(1)[0]
+    assert ws1 >= 34 * N
+
+
+def test_largest_lattice_sizes(core):
+    """nx*ny*nz just below 2^31 is accepted and its sizes do not overflow; one plane more is refused."""
+    shape = (1290, 1290, 1290)  # 2,146,689,000 nodes
+    N = 1290 ** 3
+    for prec, s, r in (("fp64", 8, 8), ("fp32", 4, 4), ("fp16", 2, 4)):
+        for nf in (0, N // 2):
+            p = core.make_params(shape, precision=prec, tau=0.8, species=True, fluid_nodes=nf)
+            ws, sb = ctypes.c_size_t(), ctypes.c_size_t()
+            assert core.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(ws)) == 0
+            assert core.lib().lbm_state_bytes(ctypes.byref(p), ctypes.byref(sb)) == 0
+            F = nf or N
+            assert sb.value >= (26 * s + 4 * r) * F
+            assert ws.value >= 2 * sb.value + 4 * N * 3
+    p = core.make_params((1291, 1290, 1290), precision="fp32", tau=0.8)
+    b = ctypes.c_size_t()
+    assert core.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == core.LBM_ERR_ARG
+    assert b"2^31" in core.lib().lbm_last_error(None)
 
 
 def _init(core, p, N, ws_bytes, rho_r0=None, theta=None, ws_ptr=256):
@@ -108,6 +162,10 @@ def test_init_rejects_bad_inputs_on_host(core):
     th = np.full(N, 4.0)
     assert _init(core, p, N, need.value, theta=th) == core.LBM_ERR_ARG
     assert b"theta" in core.lib().lbm_last_error(None)
+    # a fluid count that does not match the mask (all 64 nodes are fluid)
+    p.fluid_nodes = 63
+    assert _init(core, p, N, need.value) == core.LBM_ERR_ARG
+    assert b"fluid_nodes" in core.lib().lbm_last_error(None)
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, core):
