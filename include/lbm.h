@@ -197,7 +197,7 @@ lbm_status lbm_fields_bytes(const lbm_params* params, size_t* bytes);
  * lbm_adjoint_step_fields then reuses the fields instead of recomputing them. */
 lbm_status lbm_step_fields(lbm_ctx* ctx, void* d_fields);
 
-/* One time step (the composite update of Sec. 2: streaming, colour gradient and wetting,
+/* One time step (the composite update of Sec. II: streaming, colour gradient and wetting,
  * forcing, central-moment collision, recolouring, wall reaction, species) from the state in
  * d_src to the state in d_dst, both caller-owned device buffers of lbm_state_bytes in the layout
  * of lbm_get_state. The context's own state and step count are left as they are; its geometry,
@@ -220,8 +220,11 @@ lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const void* d_state, void* d_adj);
  * d_scratch: device memory of the scratch size from lbm_adjoint_bytes. Uses the context's
  * parameters and geometry and overwrites its per-step scratch fields (not its state). At the
  * non-smooth points of the step (minimum in the reaction cap, gradient and wetting-cone
- * guards) the derivative of the branch taken is used. Stream-ordered; errors: LBM_ERR_ARG for
- * null or aliased buffers, LBM_ERR_HIP. */
+ * guards) the derivative of the branch taken is used. With FP16/BF16 deviation storage the
+ * adjoint is that of the FP32 arithmetic at the stored states, the storage rounding taken as the
+ * identity (per-node contact-angle gradients are then usable in FP16 but not in BF16; integral
+ * quantities such as dL/dxi hold in both). Stream-ordered; errors: LBM_ERR_ARG for null or
+ * aliased buffers, LBM_ERR_HIP. */
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* d_state, const void* d_adj_in, void* d_adj_out,
                             void* d_scratch, double* d_grad_theta, double* d_grad_xi);
 

@@ -1,13 +1,14 @@
 """GPU adjoint (lbm_adjoint_seed / lbm_adjoint_step) and the checkpointed autograd function.
 
-All in FP64 storage. Pins, independent of the adjoint code:
+FP64 storage unless stated. Pins, independent of the adjoint code:
   * one step: <lambda_t, dS> against central differences of the forward step (FP64 library);
     theta and xi parts likewise;
   * many steps: directional derivatives of L = m^p(T) - m^p(0) against the oracle's forward-mode
     dual numbers (exact derivatives of the FP64 reference step);
   * checkpoint-and-recompute gives the same gradient bit for bit as keeping every state;
   * per-node contact-angle derivatives on sampled wetting nodes against central differences
-    (eps = 1e-4 rad) of the FP64 forward run.
+    (eps = 1e-4 rad) of the FP64 forward run;
+  * the FP32-arithmetic adjoint (FP32, FP16 and BF16 storage) against the FP64 adjoint.
 """
 import numpy as np
 import pytest
@@ -269,3 +270,34 @@ def test_adjoint96_crop_gradient_against_oracle_duals(core, oracle_mod):
     assert abs(Lg - L) < 1e-10 * abs(L)
     for a, b in zip(ad, dL):
         assert abs(a - b) < 1e-8 * abs(b) + 1e-14, (a, b)
+
+
+@pytest.mark.parametrize("prec,tol_th,tol_xi,tol_L", [("fp32", 1e-2, 1e-5, 5e-6), ("fp16", 3e-2, 1e-4, 3e-5),
+                                                      ("bf16", None, 1e-2, 1e-4)])
+def test_reduced_precision_adjoint_against_fp64(core, prec, tol_th, tol_xi, tol_L):
+    """The adjoint in FP32 arithmetic (FP32 storage, or FP16/BF16 deviation storage whose rounding
+    the adjoint takes as the identity) against the FP64 adjoint of the same problem: 24^3 porous
+    mask, 100 steps, checkpoint 10. The bounds are about 6x the errors measured on this case
+    (FP32: dL/dtheta 1.6e-3 relative L2, dL/dxi 1.1e-6, L 5.5e-7; FP16: 4.3e-3, 1.2e-5, 3.2e-6;
+    BF16: dL/dxi 9.1e-4, L 1.5e-5). BF16's 8-bit deviations leave the per-node contact-angle
+    gradient without a usable bound (about 0.5 relative): only the integral quantities are
+    checked there."""
+    from paper_2608_15781_amd import autograd as ag
+
+    n, T, seed = 24, 100, 43
+    solid, theta, rr0, rp0 = _case(n, seed)
+    res = {}
+    for p in ("fp64", prec):
+        sim = core.Lbm((n, n, n), solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, xi=0.02, precision=p,
+                       tau_species=0.8, **KW)
+        L, cps, fin = ag.forward_states(sim, T, 10)
+        g, gx, _ = ag.adjoint_gradients(sim, T, 10, cps, fin)
+        res[p] = (L, g.cpu().numpy(), float(gx))
+    (L0, g0, x0), (L, g, x) = res["fp64"], res[prec]
+    e_th = np.linalg.norm(g - g0) / np.linalg.norm(g0)
+    e_xi = abs(x - x0) / abs(x0)
+    e_L = abs(L - L0) / abs(L0)
+    print("%s adjoint vs fp64: dtheta %.2e dxi %.2e L %.2e" % (prec, e_th, e_xi, e_L), flush=True)
+    assert e_xi < tol_xi and e_L < tol_L
+    if tol_th is not None:
+        assert e_th < tol_th
