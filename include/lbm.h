@@ -188,7 +188,8 @@ lbm_status lbm_kernel_times(lbm_ctx* ctx, double* kernel_ms, int64_t* steps);
 lbm_status lbm_adjoint_bytes(const lbm_params* params, size_t* adj_bytes, size_t* scratch_bytes);
 
 /* Size of a buffer for the forward fields of one level (rho^N, the realigned normal n* with
- * |grad rho^N|, rho^m), for lbm_step_fields and lbm_adjoint_step_fields. */
+ * |grad rho^N|, the normal before realignment at wetting nodes, rho^m), for lbm_step_fields,
+ * lbm_step_from and lbm_adjoint_step_fields. */
 lbm_status lbm_fields_bytes(const lbm_params* params, size_t* bytes);
 
 /* One time step, enqueued like lbm_step_async, that computes its level-t fields (the state

@@ -3,8 +3,9 @@
 // For the step map S_{t+1} = Phi(S_t; theta, xi) of step_kernels.hpp, one adjoint step turns
 // lambda_{t+1} = dL/dS_{t+1} into lambda_t = (dPhi/dS_t)^T lambda_{t+1} and accumulates
 // (dPhi/dtheta)^T lambda_{t+1} per node and (dPhi/dxi)^T lambda_{t+1}. The forward fields of
-// level t (rho^N, rho^m, n*, |G|) are first recomputed from S_t by the forward colour,
-// extrapolation and normal kernels; the reverse pass then runs
+// level t (rho^N, rho^m, n*, |G|, and the normal before realignment at wetting nodes) come from
+// the forward colour, extrapolation and normal kernels, run on S_t here or kept by the
+// recomputing step; the reverse pass then runs
 //   k_adj_collide   reverse of the collide kernel at each fluid node; the pull transposes to a
 //                   scatter that is a bijection on (node, direction), so every adjoint population
 //                   is written exactly once, without atomics (and the output needs no clearing;
@@ -35,7 +36,7 @@ struct AdjArgs {
   R* lrn;            // d/d rho^N: collide part, then total (fluid and extrapolated solid nodes)
   R* lnc;            // 3 planes: d/d n* from the collide (including its own curvature terms)
   R* lglen;          // d/d |G|
-  R* lH;             // d/d H
+  R* lHn;            // per fluid id 4-vector (d/d H, n*): what the curvature transpose gathers
   R* lG;             // 3 planes: d/d G
   R* lrr;            // d/d rho^r of the colour pass
   R* lrm;            // d/d rho^m of the colour pass
@@ -522,7 +523,7 @@ __global__ __launch_bounds__(kBlock, P == 0 ? 1 : 3) void k_adj_collide(StepArgs
     J.lnc[N + n] = l_n[1];
     J.lnc[2 * N + n] = l_n[2];
     J.lglen[n] = l_glen;
-    J.lH[n] = has_n ? l_H : R(0);
+    st4(J.lHn, t, has_n ? l_H : R(0), nn[0], nn[1], nn[2]);
   }
   double s5[5] = {gxi, 0, 0, 0, 0};
   block_reduce5(s5, J.partials);
@@ -546,49 +547,44 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
   const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
+  // Every load of this node's own entries is issued here, before any is needed, so that they
+  // share one memory round trip with the neighbours' ids (the wetting entries are read at every
+  // node and used only at wetting nodes): the forward normal pass's n* and |G|, the normal
+  // before realignment, the wetting data, dL/d|G| and the running dL/dtheta.
+  const typename V4<R>::T nsv = ld4(A.nst, t);
+  const typename V4<R>::T rv = ld4(A.nraw, t);
+  const typename V4<R>::T wv = ld4(A.wet, t);
+  const R lgl = J.lglen[n];
+  const double gth0 = J.gtheta[n];
   R mu[3] = {J.lnc[n], J.lnc[N + n], J.lnc[2 * N + n]};
   // H(x) at each fluid neighbour x = y - c_i used n*(x + c_i) = n*(y):
-  // dH(x)/dn*_a(y) = -3 w_i (c_ia - n_a(x) (n(x).c_i)).
-  // Loads first, in two dependent rounds for all directions at once (dH/d and fluid id, then the
-  // normal); a solid y - c_i reads this node's own entries and is discarded.
-  R lh[18];
+  // dH(x)/dn*_a(y) = -3 w_i (c_ia - n_a(x) (n(x).c_i)). The fluid ids of all 18 neighbours
+  // first, then one gather of (dL/dH, n*) each; a solid y - c_i reads this node's own entry
+  // and is discarded.
   int mid[18];
 #pragma unroll
-  for (int i = 0; i < 18; ++i) {
-    const int m = ((inf >> i) & 1u) ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i]);
-    lh[i] = J.lH[m];
-    mid[i] = A.fid[m];
-  }
+  for (int i = 0; i < 18; ++i) mid[i] = A.fid[((inf >> i) & 1u) ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
 #pragma unroll
   for (int i = 0; i < 18; ++i) {
-    const typename V4<R>::T qv = ld4(A.nst, mid[i]);
-    const bool use = !((inf >> i) & 1u) && lh[i] != R(0);
-    const R q0 = qv.x, q1 = qv.y, q2 = qv.z;
+    const typename V4<R>::T qv = ld4(J.lHn, mid[i]);
+    const R lh = qv.x, q0 = qv.y, q1 = qv.z, q2 = qv.w;
+    const bool use = !((inf >> i) & 1u) && lh != R(0);
     const R cn = R(D::cx[i]) * q0 + R(D::cy[i]) * q1 + R(D::cz[i]) * q2;
-    const R w3 = R(-3.0 * D::w(i)) * lh[i];
+    const R w3 = R(-3.0 * D::w(i)) * lh;
     mu[0] = use ? mu[0] + w3 * (R(D::cx[i]) - q0 * cn) : mu[0];
     mu[1] = use ? mu[1] + w3 * (R(D::cy[i]) - q1 * cn) : mu[1];
     mu[2] = use ? mu[2] + w3 * (R(D::cz[i]) - q2 * cn) : mu[2];
   }
-  // Recompute the raw gradient and the normal of this node (as k_normal).
-  R g[3] = {0, 0, 0};
-#pragma unroll
-  for (int j = 0; j < 9; ++j) {
-    const int p = D::half[j];
-    const R d = rn_diff(A.rhoN[nb.at(D::cx[p], D::cy[p], D::cz[p])], A.rhoN[nb.at(-D::cx[p], -D::cy[p], -D::cz[p])]);
-    const R c3w = R(3.0 * D::w(p));
-    if (D::cx[p]) g[0] += c3w * R(D::cx[p]) * d;
-    if (D::cy[p]) g[1] += c3w * R(D::cy[p]) * d;
-    if (D::cz[p]) g[2] += c3w * R(D::cz[p]) * d;
-  }
-  const R len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  // The unit normal of this node: n* unless the wetting realignment changed it, in which case
+  // the normal pass kept the one before realignment.
+  const R len = nsv.w;
   R lG[3] = {0, 0, 0};
   if (len > A.eps) {
     const R il = R(1) / len;
-    const R nv[3] = {g[0] * il, g[1] * il, g[2] * il};
+    R nv[3] = {nsv.x, nsv.y, nsv.z};
     R ln[3] = {mu[0], mu[1], mu[2]};
     if (inf & kWet) {
-      const typename V4<R>::T wv = ld4(A.wet, t);
+      nv[0] = rv.x; nv[1] = rv.y; nv[2] = rv.z;
       const R sx = wv.x, sy = wv.y, sz = wv.z;
       if (sx * sx + sy * sy + sz * sz > R(0.5)) {
         const R ct = wv.w;
@@ -606,12 +602,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
 #pragma unroll
           for (int a = 0; a < 3; ++a) ln[a] = b * mu[a] + mns * (b * cp / sp * tv[a] - b * ns[a]) - mn * (b / sp) * tv[a];
           // d n*/d theta = (-sin(theta) - cos(theta) cos(theta')/sin(theta')) n_s + (cos(theta)/sin(theta')) n
-          J.gtheta[n] += double(mns * (-st - ct * cp / sp) + mn * (ct / sp));
+          J.gtheta[n] = gth0 + double(mns * (-st - ct * cp / sp) + mn * (ct / sp));
         }
       }
     }
     const R lnn = ln[0] * nv[0] + ln[1] * nv[1] + ln[2] * nv[2];
-    const R lgl = J.lglen[n];
 #pragma unroll
     for (int a = 0; a < 3; ++a) lG[a] = (ln[a] - lnn * nv[a]) * il + lgl * nv[a];
   }

@@ -100,13 +100,14 @@ Layout make_layout(const lbm_params& p) {
 
 struct AdjLayout {
   size_t adj_bytes;                                                       // one adjoint state
-  size_t lrn, lnc, lglen, lH, lG, lrr, lrm, lgo, rmv, partials, sum, total;  // scratch offsets
+  size_t lrn, lnc, lglen, lHn, lG, lrr, lrm, lgo, rmv, nraw, partials, sum, total;  // scratch offsets
 };
 
 // Forward fields of one level, kept by lbm_step_fields for lbm_adjoint_step_fields: rho^N (dense),
-// n* and |G| (per fluid id), rho^m (dense).
+// n* and |G| (per fluid id), the normal before realignment at wetting nodes (per fluid id),
+// rho^m (dense).
 struct FieldLayout {
-  size_t rhoN, nst, rm, total;
+  size_t rhoN, nst, nraw, rm, total;
 };
 
 FieldLayout make_field_layout(const lbm_params& p) {
@@ -116,6 +117,7 @@ FieldLayout make_field_layout(const lbm_params& p) {
   size_t o = 0;
   F.rhoN = o; o = align_up(o + r * N);
   F.nst = o; o = align_up(o + 4 * r * fluid_bound(p));
+  F.nraw = o; o = align_up(o + 4 * r * fluid_bound(p));
   F.rm = o; o = align_up(o + r * N);
   F.total = o;
   return F;
@@ -130,12 +132,13 @@ AdjLayout make_adj_layout(const lbm_params& p) {
   A.lrn = o; o = align_up(o + r * N);
   A.lnc = o; o = align_up(o + 3 * r * N);
   A.lglen = o; o = align_up(o + r * N);
-  A.lH = o; o = align_up(o + r * N);
+  A.lHn = o; o = align_up(o + 4 * r * fluid_bound(p));
   A.lG = o; o = align_up(o + 3 * r * N);
   A.lrr = o; o = align_up(o + r * N);
   A.lrm = o; o = align_up(o + r * N);
   A.lgo = o; o = align_up(o + r * N);
   A.rmv = o; o = align_up(o + r * N);
+  A.nraw = o; o = align_up(o + 4 * r * fluid_bound(p));
   A.partials = o; o = align_up(o + 5 * sizeof(double) * size_t(make_layout(p).nblocks));
   A.sum = o; o = align_up(o + 5 * sizeof(double));
   A.total = o;
@@ -442,6 +445,7 @@ void use_fields(lbm_ctx* c, StepArgs<P>& A, void* fields) {
   char* fb = static_cast<char*>(fields);
   A.rhoN = reinterpret_cast<R*>(fb + FL.rhoN);
   A.nst = reinterpret_cast<R*>(fb + FL.nst);
+  A.nraw = reinterpret_cast<R*>(fb + FL.nraw);
   A.rm_out = reinterpret_cast<R*>(fb + FL.rm);
 }
 
@@ -626,6 +630,7 @@ lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* fields, co
   char* sc = static_cast<char*>(scratch);
   StepArgs<P> A = make_args_from<P>(c, state);
   A.rm_out = reinterpret_cast<R*>(sc + AL.rmv);
+  A.nraw = reinterpret_cast<R*>(sc + AL.nraw);
   if (fields)  // level-t fields kept by the forward step: no recomputation
     use_fields<P>(c, A, const_cast<void*>(fields));
   AdjArgs<R> J;
@@ -634,7 +639,7 @@ lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* fields, co
   J.lrn = reinterpret_cast<R*>(sc + AL.lrn);
   J.lnc = reinterpret_cast<R*>(sc + AL.lnc);
   J.lglen = reinterpret_cast<R*>(sc + AL.lglen);
-  J.lH = reinterpret_cast<R*>(sc + AL.lH);
+  J.lHn = reinterpret_cast<R*>(sc + AL.lHn);
   J.lG = reinterpret_cast<R*>(sc + AL.lG);
   J.lrr = reinterpret_cast<R*>(sc + AL.lrr);
   J.lrm = reinterpret_cast<R*>(sc + AL.lrm);

@@ -161,7 +161,7 @@ struct StepArgs {
   using S = typename Prec<P>::S;
   using R = typename Prec<P>::R;
   int nx, ny, nz, N;
-  size_t ps;              // plane stride of the state and adjoint planes (>= N elements)
+  size_t ps;              // plane stride of the state and adjoint planes (>= fluid nodes)
   Geom geo;
   const int* fluid;       // dense indices of the fluid nodes, in increasing order
   const uint32_t* finfo;  // their info words
@@ -181,6 +181,8 @@ struct StepArgs {
   R* rhoN;       // 1 plane, rho^N in the form of rn_value
   R* rm_out;     // optional: rho^m of each fluid node (adjoint recompute)
   R* nst;        // per fluid id 4-vector (n*_x, n*_y, n*_z, |grad rho^N|)
+  R* nraw;       // optional: per fluid id, the unit normal before the wetting realignment at
+                 // wetting nodes (kept for the adjoint; elsewhere it equals n*)
   const R* wet;  // per fluid id 4-vector (n_s, cos(theta))
   double* partials;
   double* ring_row;  // 5 doubles of this step
@@ -350,6 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
     const R il = R(1) / len;
     nv[0] = g[0] * il; nv[1] = g[1] * il; nv[2] = g[2] * il;
     if (inf & kWet) {
+      if (A.nraw) st4(A.nraw, t, nv[0], nv[1], nv[2], R(0));
       const typename V4<R>::T wv = ld4(A.wet, t);
       const R sx = wv.x, sy = wv.y, sz = wv.z;
       if (sx * sx + sy * sy + sz * sz > R(0.5)) {
