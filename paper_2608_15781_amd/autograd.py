@@ -7,6 +7,9 @@ the library (lbm_adjoint_seed / lbm_adjoint_step) with checkpoint-and-recompute 
 forward pass keeps the state every ``problem["checkpoint"]`` steps; the backward pass restores
 each checkpoint in reverse order, recomputes that segment's states, and runs the adjoint steps
 backwards through it. Memory: one state per checkpoint plus one segment of states.
+``problem["checkpoint"] = 0`` keeps every level instead (state and forward fields, written
+straight into buffers of their own by the forward pass), and the backward pass recomputes
+nothing: faster, for T levels of memory.
 
 theta: per-node contact angles in radians, shape (nz, ny, nx) (only wetting nodes matter);
 xi: scalar reaction rate. Both are float64 tensors; gradients come back in float64 on the same
@@ -42,6 +45,48 @@ def forward_states(sim, steps, checkpoint):
         if t < steps:
             cps[t] = sim.get_state()
     return conv, cps, sim.get_state()
+
+
+def _product_mass(sim):
+    return float(sim.moments()["rho_p"].double().sum())
+
+
+def forward_keep_all(sim, steps):
+    """Runs `steps` steps keeping every level: returns (L, (states S_0..S_{T-1}, their level
+    fields), final state S_T) and leaves the context at S_T. The steps go from buffer to buffer
+    (lbm_step_from), so nothing is copied; the colour mass changes only by the wall reaction, so
+    L = m^p(T) - m^p(0) is read from the end states. Memory: T states and T field buffers."""
+    mp0 = _product_mass(sim)
+    t0 = sim.steps_done
+    sb, fb = sim.state_bytes, sim.fields_bytes()  # multiples of 256 bytes
+    # one allocation for all levels, sliced: levels 1..T, then the fields of levels 0..T-1
+    with torch.cuda.stream(sim.stream):
+        block = torch.empty(steps * (sb + fb), dtype=torch.uint8, device=sim.device)
+    states = [sim.get_state(sync=False)] + [block[k * sb:(k + 1) * sb] for k in range(steps)]
+    base = steps * sb
+    fields = [block[base + k * fb:base + (k + 1) * fb] for k in range(steps)]
+    sim.step_chain(states, fields)
+    final = states.pop()
+    sim.set_state(final, t0 + steps)
+    return _product_mass(sim) - mp0, (states, fields), final
+
+
+def adjoint_gradients_keep_all(sim, levels, final_state):
+    """Reverse sweep over levels kept by forward_keep_all (no recomputation); returns
+    (dL/dtheta per node, dL/dxi, lambda_0), bitwise the same as adjoint_gradients."""
+    states, fields = levels
+    dev = sim.device
+    lam = sim.new_adjoint()
+    lam2 = sim.new_adjoint()
+    scratch = sim.new_scratch()
+    gth = torch.zeros(sim.N, dtype=torch.float64, device=dev)
+    gxi = torch.zeros(1, dtype=torch.float64, device=dev)
+    sim.adjoint_seed(final_state, lam)
+    for t in range(len(states) - 1, -1, -1):
+        sim.adjoint_step(states[t], lam, lam2, scratch, gth, gxi, fields=fields[t])
+        lam, lam2 = lam2, lam
+    torch.cuda.synchronize(dev)
+    return gth, gxi[0], lam
 
 
 def adjoint_gradients(sim, steps, checkpoint, cps, final_state, keep_fields=True):
@@ -86,14 +131,20 @@ class GasProduction(torch.autograd.Function):
     def forward(ctx, theta, xi, problem):
         sim = _build(theta, xi, problem)
         steps, ck = int(problem["steps"]), int(problem.get("checkpoint", 20))
-        L, cps, final = forward_states(sim, steps, ck)
+        if ck == 0:
+            L, cps, final = forward_keep_all(sim, steps)
+        else:
+            L, cps, final = forward_states(sim, steps, ck)
         ctx.sim, ctx.cps, ctx.final, ctx.steps, ctx.ck = sim, cps, final, steps, ck
         ctx.theta_shape, ctx.theta_device, ctx.xi_device = theta.shape, theta.device, xi.device
         return torch.tensor(L, dtype=torch.float64, device=theta.device)
 
     @staticmethod
     def backward(ctx, gL):
-        gth, gxi, _ = adjoint_gradients(ctx.sim, ctx.steps, ctx.ck, ctx.cps, ctx.final)
+        if ctx.ck == 0:
+            gth, gxi, _ = adjoint_gradients_keep_all(ctx.sim, ctx.cps, ctx.final)
+        else:
+            gth, gxi, _ = adjoint_gradients(ctx.sim, ctx.steps, ctx.ck, ctx.cps, ctx.final)
         g = gL.to(torch.float64)
         dtheta = (g.to(gth.device) * gth).view(ctx.theta_shape).to(ctx.theta_device)
         dxi = (g.to(gxi.device) * gxi).reshape(()).to(ctx.xi_device)

@@ -260,6 +260,28 @@ class Lbm:
             fp = fields.data_ptr()
         self._check(lib().lbm_step_from(self._h, src.data_ptr(), dst.data_ptr(), fp), self._h)
 
+    def step_chain(self, states, fields=None):
+        """len(states) - 1 enqueued steps, states[k] -> states[k + 1] (lbm_step_from), keeping the
+        level-k fields in fields[k] if given. The buffers are checked once, before the first
+        step, and the steps are issued with their raw pointers."""
+        sb = self.state_bytes
+        for k, s in enumerate(states):
+            self._need(s, sb, "state %d" % k)
+        fps = [None] * (len(states) - 1)
+        if fields is not None:
+            if len(fields) != len(states) - 1:
+                raise ValueError("need one fields buffer per step")
+            fb = self.fields_bytes()
+            for k, f in enumerate(fields):
+                self._need(f, fb, "fields %d" % k)
+            fps = [f.data_ptr() for f in fields]
+        ptrs = [s.data_ptr() for s in states]
+        fn, h = lib().lbm_step_from, self._h
+        for k in range(len(states) - 1):
+            st = fn(h, ptrs[k], ptrs[k + 1], fps[k])
+            if st != LBM_OK:
+                self._check(st, h)
+
     def get_state(self, sync=True):
         """A copy of the state (uint8 tensor of state_bytes). With sync=False the copy is only
         enqueued on the context's stream (work on that stream sees it complete)."""

@@ -5,7 +5,7 @@ FP64 storage unless stated. Pins, independent of the adjoint code:
     theta and xi parts likewise;
   * many steps: directional derivatives of L = m^p(T) - m^p(0) against the oracle's forward-mode
     dual numbers (exact derivatives of the FP64 reference step);
-  * checkpoint-and-recompute gives the same gradient bit for bit as keeping every state;
+  * checkpoint-and-recompute gives the same gradient bit for bit as keeping every level;
   * per-node contact-angle derivatives on sampled wetting nodes against central differences
     (eps = 1e-4 rad) of the FP64 forward run;
   * the FP32-arithmetic adjoint (FP32, FP16 and BF16 storage) against the FP64 adjoint.
@@ -146,6 +146,16 @@ def test_gradient_matches_oracle_duals_and_checkpointing(core, oracle_mod):
     assert torch.equal(gth2, gth) and float(gxi2) == float(gxi)
     gth3, gxi3, _ = ag.adjoint_gradients(sim2, T, 7, cps2, final2, keep_fields=False)
     assert torch.equal(gth3, gth) and float(gxi3) == float(gxi)
+    # keeping every level in the forward pass instead: the same gradient bit for bit, the same
+    # final state, and L (read from the end states' product mass) equal to the conversion sum
+    sim3 = _sim(core, n, solid, theta, rr0, rp0, xi)
+    L3, levels, final3 = ag.forward_keep_all(sim3, T)
+    gth4, gxi4, _ = ag.adjoint_gradients_keep_all(sim3, levels, final3)
+    assert torch.equal(gth4, gth) and float(gxi4) == float(gxi)
+    assert sim3.steps_done == T
+    for a_, b_ in zip(sim3.state_parts(final3), sim.state_parts(final)):
+        assert torch.equal(a_, b_)
+    assert abs(L3 - Lg) <= 1e-11 * abs(Lg), (L3, Lg)
     # the autograd function
     th_t = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
     xi_t = torch.tensor(xi, dtype=torch.float64, requires_grad=True)
@@ -153,9 +163,14 @@ def test_gradient_matches_oracle_duals_and_checkpointing(core, oracle_mod):
                    params=dict(tau_species=0.8, **KW))
     Lt = ag.gas_production(th_t, xi_t, problem)
     Lt.backward()
-    assert abs(float(Lt) - Lg) <= 1e-12 * abs(Lg)
+    assert abs(float(Lt.detach()) - Lg) <= 1e-12 * abs(Lg)
     assert np.array_equal(th_t.grad.numpy().ravel(), g)
     assert float(xi_t.grad) == float(gxi)
+    th_k = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    xi_k = torch.tensor(xi, dtype=torch.float64, requires_grad=True)
+    Lk = ag.gas_production(th_k, xi_k, dict(problem, checkpoint=0))
+    Lk.backward()
+    assert np.array_equal(th_k.grad.numpy().ravel(), g) and float(xi_k.grad) == float(gxi)
 
 
 def test_contact_angle_gradient_finite_differences_on_wall_nodes(core):
