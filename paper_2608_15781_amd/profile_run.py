@@ -1,4 +1,4 @@
-"""Profiling driver and summariser for rocprofv3.
+"""Profiling program and summariser for rocprofv3.
 
 Run under the profiler (the program itself follows ``--``):
 
@@ -7,7 +7,7 @@ Run under the profiler (the program itself follows ``--``):
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o fetch -- python3 -m ... (same args)
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT -o write -- python3 -m ... (same args)
 
-The driver runs the benchmark workload for the given number of steps, then a plain device-to-
+The program runs the benchmark workload for the given number of steps, then a plain device-to-
 device copy of a known size (``--copy-mib``), whose counter readings calibrate the byte counters.
 ``python3 -m paper_2608_15781_amd.profile_run report --precision P --fluid-nodes F TRACE FETCH WRITE``
 turns the three CSV folders into the short markdown summary kept under ``profiles/``.
