@@ -177,6 +177,41 @@ def test_tiny_and_degenerate(core, oracle_mod):
     assert np.all(r == 0)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp16", HALF_TOL)])
+def test_sparse_fluid_and_isolated_node(core, oracle_mod, precision, tol):
+    """Low porosity, where the state is smaller than what initialisation stages per node (34 B):
+    a 14x12x10 lattice with about 8% fluid in two thin channels plus isolated fluid pockets,
+    every feature on; and a single fluid node enclosed by solid on all 18 links, whose
+    populations bounce back in place (rest state unchanged to rounding)."""
+    shape = (14, 12, 10)
+    nx, ny, nz = shape
+    solid = np.ones((nz, ny, nx), np.uint8)
+    solid[4, 5, :] = 0          # channel along x (open inlet/outlet planes)
+    solid[2:8, 8, 3] = 0        # channel along z
+    solid[7, 2, 9] = 0          # isolated single node
+    solid[1, 1, 1] = solid[1, 1, 2] = 0  # isolated pair
+    rng = np.random.default_rng(31)
+    theta = np.deg2rad(rng.uniform(40, 140, solid.shape))
+    rr0 = (1 - solid) * (rng.uniform(size=solid.shape) > 0.5)
+    rp0 = (1 - solid) - rr0
+    assert (solid == 0).mean() < 0.1
+    gpu, ref = _pair(core, oracle_mod, shape, solid=solid, theta=theta, rho_r0=rr0.astype(float),
+                     rho_p0=rp0.astype(float), precision=precision, **FULL_KW)
+    gpu.step(40)
+    ref.step(40)
+    _compare(gpu, ref, tol, "sparse %s" % precision)
+    # one fluid node closed on every link: at rest, in equilibrium, it stays so
+    s1 = np.ones((5, 5, 5), np.uint8)
+    s1[2, 2, 2] = 0
+    one = core.Lbm((5, 5, 5), solid=s1, rho_r0=(1 - s1).astype(float), rho_p0=0.0, precision=precision,
+                   tau=0.8, sigma=0.02, beta=0.7, species=True, tau_species=0.9)
+    before = one.populations()[0][:, 62].double().cpu().numpy()
+    red = one.step(25)
+    after = one.populations()[0][:, 62].double().cpu().numpy()
+    assert np.abs(after - before).max() <= 1e-6 * np.abs(before).max()
+    assert abs(red[-1, 0] - 1.0) < 1e-6 and red[:, 4].max() == 0
+
+
 def test_geometry_matches_reference(core, oracle_mod):
     """Static geometry: NN, wetting set, reactive set and the E8 solid normal."""
     shape = (20, 18, 16)
