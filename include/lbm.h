@@ -224,8 +224,9 @@ lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const void* d_state, void* d_adj);
  * guards) the derivative of the branch taken is used. With FP16/BF16 deviation storage the
  * adjoint is that of the FP32 arithmetic at the stored states, the storage rounding taken as the
  * identity (per-node contact-angle gradients are then usable in FP16 but not in BF16; integral
- * quantities such as dL/dxi hold in both). Stream-ordered; errors: LBM_ERR_ARG for null or
- * aliased buffers, LBM_ERR_HIP. */
+ * quantities such as dL/dxi hold in both). Stream-ordered; errors: LBM_ERR_ARG for a null
+ * buffer or when a buffer the step writes (d_adj_out, d_scratch) overlaps another of its
+ * buffers, LBM_ERR_HIP. */
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* d_state, const void* d_adj_in, void* d_adj_out,
                             void* d_scratch, double* d_grad_theta, double* d_grad_xi);
 

@@ -26,6 +26,12 @@ constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Byte ranges [a, a + na) and [b, b + nb) of device memory overlap.
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+
 size_t store_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2); }
 size_t real_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 
@@ -670,6 +676,23 @@ lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* fields, co
   return LBM_OK;
 }
 
+// The buffers one adjoint step writes (adjoint output, scratch) must not overlap anything it
+// reads or writes (state, fields, adjoint input, each other).
+lbm_status check_adjoint_buffers(lbm_ctx* c, const void* state, const void* fields, const void* lin,
+                                 const void* lout, const void* scratch) {
+  const AdjLayout AL = make_adj_layout(c->p);
+  const size_t sb = c->L.state_bytes, ab = AL.adj_bytes, cb = AL.total;
+  const size_t fb = make_field_layout(c->p).total;
+  if (overlap(lin, ab, lout, ab)) return fail(c, LBM_ERR_ARG, "adjoint input and output overlap");
+  if (overlap(lout, ab, state, sb) || overlap(scratch, cb, state, sb))
+    return fail(c, LBM_ERR_ARG, "an adjoint buffer overlaps the state");
+  if (overlap(scratch, cb, lin, ab) || overlap(scratch, cb, lout, ab))
+    return fail(c, LBM_ERR_ARG, "the scratch buffer overlaps an adjoint buffer");
+  if (fields && (overlap(fields, fb, lout, ab) || overlap(fields, fb, scratch, cb)))
+    return fail(c, LBM_ERR_ARG, "the fields buffer overlaps an adjoint output");
+  return LBM_OK;
+}
+
 #define DISPATCH(ctx, fn, ...)                                   \
   switch ((ctx)->p.precision) {                                  \
     case LBM_FP64: return fn<0>((ctx), __VA_ARGS__);             \
@@ -890,14 +913,11 @@ lbm_status lbm_step_fields(lbm_ctx* c, void* d_fields) {
 lbm_status lbm_step_from(lbm_ctx* c, const void* d_src, void* d_dst, void* d_fields) {
   if (!c) return LBM_ERR_ARG;
   if (!d_src || !d_dst) return fail(c, LBM_ERR_ARG, "source and destination states are required");
-  const char* s0 = static_cast<const char*>(d_src);
-  const char* d0 = static_cast<const char*>(d_dst);
-  const size_t nb = c->L.state_bytes;
-  if (s0 < d0 + nb && d0 < s0 + nb) return fail(c, LBM_ERR_ARG, "source and destination states overlap");
+  const size_t sb = c->L.state_bytes;
+  if (overlap(d_src, sb, d_dst, sb)) return fail(c, LBM_ERR_ARG, "source and destination states overlap");
   if (d_fields) {
-    const char* f0 = static_cast<const char*>(d_fields);
     const size_t fb = make_field_layout(c->p).total;
-    if ((f0 < d0 + nb && d0 < f0 + fb) || (f0 < s0 + nb && s0 < f0 + fb))
+    if (overlap(d_fields, fb, d_dst, sb) || overlap(d_fields, fb, d_src, sb))
       return fail(c, LBM_ERR_ARG, "the fields buffer overlaps a state");
   }
   DISPATCH(c, launch_step_from, d_src, d_dst, d_fields);
@@ -999,7 +1019,8 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* d_state, const void* d_adj_i
   if (!c) return LBM_ERR_ARG;
   if (!d_state || !d_adj_in || !d_adj_out || !d_scratch || !d_grad_theta || !d_grad_xi)
     return fail(c, LBM_ERR_ARG, "all buffers are required");
-  if (d_adj_in == d_adj_out) return fail(c, LBM_ERR_ARG, "adjoint input and output must differ");
+  const lbm_status chk = check_adjoint_buffers(c, d_state, nullptr, d_adj_in, d_adj_out, d_scratch);
+  if (chk != LBM_OK) return chk;
   const void* no_fields = nullptr;
   DISPATCH(c, launch_adj_step, d_state, no_fields, d_adj_in, d_adj_out, d_scratch, d_grad_theta, d_grad_xi);
 }
@@ -1009,7 +1030,8 @@ lbm_status lbm_adjoint_step_fields(lbm_ctx* c, const void* d_state, const void* 
   if (!c) return LBM_ERR_ARG;
   if (!d_state || !d_fields || !d_adj_in || !d_adj_out || !d_scratch || !d_grad_theta || !d_grad_xi)
     return fail(c, LBM_ERR_ARG, "all buffers are required");
-  if (d_adj_in == d_adj_out) return fail(c, LBM_ERR_ARG, "adjoint input and output must differ");
+  const lbm_status chk = check_adjoint_buffers(c, d_state, d_fields, d_adj_in, d_adj_out, d_scratch);
+  if (chk != LBM_OK) return chk;
   DISPATCH(c, launch_adj_step, d_state, d_fields, d_adj_in, d_adj_out, d_scratch, d_grad_theta, d_grad_xi);
 }
 

@@ -316,3 +316,31 @@ def test_reduced_precision_adjoint_against_fp64(core, prec, tol_th, tol_xi, tol_
     assert e_xi < tol_xi and e_L < tol_L
     if tol_th is not None:
         assert e_th < tol_th
+
+
+def test_adjoint_refuses_overlapping_buffers(core):
+    """Checked on the host before any launch: the adjoint output overlapping the input, and the
+    scratch overlapping the state, are refused (through the C ABI, bypassing the binding)."""
+    import torch
+
+    n = 8
+    solid, theta, rr0, rp0 = _case(n, 5)
+    sim = _sim(core, n, solid, theta, rr0, rp0, 0.01)
+    state = sim.get_state()
+    ab, scr = sim.adjoint_bytes()
+    big = torch.zeros(2 * ab + 4096, dtype=torch.uint8, device="cuda:0")
+    scratch = sim.new_scratch()
+    gth = torch.zeros(sim.N, dtype=torch.float64, device="cuda:0")
+    gxi = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    L = core.lib()
+    p = big.data_ptr()
+    st = L.lbm_adjoint_step(sim._h, state.data_ptr(), p, p + 256, scratch.data_ptr(), gth.data_ptr(), gxi.data_ptr())
+    assert st == core.LBM_ERR_ARG and b"overlap" in L.lbm_last_error(sim._h)
+    st = L.lbm_adjoint_step(sim._h, state.data_ptr(), p, p + ab + 256, state.data_ptr() + 512, gth.data_ptr(),
+                            gxi.data_ptr())
+    assert st == core.LBM_ERR_ARG and b"overlap" in L.lbm_last_error(sim._h)
+    # disjoint buffers are accepted
+    st = L.lbm_adjoint_step(sim._h, state.data_ptr(), p, p + ab + 256, scratch.data_ptr(), gth.data_ptr(),
+                            gxi.data_ptr())
+    assert st == core.LBM_OK
+    torch.cuda.synchronize()
