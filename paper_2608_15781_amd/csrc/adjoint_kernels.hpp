@@ -13,8 +13,9 @@
 //                   zeroed by k_adj_final)
 //   k_adj_normal    curvature transpose (gather of the neighbours' dH/dn*), then the normal and
 //                   Akai realignment reversed to d/dG; accumulates dL/dtheta
-//   k_adj_grad      transpose of the isotropic gradient stencil (gather), fluid and solid nodes
-//   k_adj_colour    transpose of the colour extrapolation into solids, then d rho^N -> d rho^r, d rho^m
+//   k_adj_grad_ext  transpose of the isotropic gradient stencil (gather) at solid nodes
+//   k_adj_colour    the same transpose at fluid nodes, the colour extrapolation into solids
+//                   transposed, then d rho^N -> d rho^r, d rho^m
 //   k_adj_final     the colour pass's dependence on f^m, a and v of each pull source (gather)
 // Non-smooth points (the minimum in the reaction cap, the |G| and wetting-cone guards) take the
 // derivative of the branch the forward step took. Gradients are accumulated in FP64.
@@ -33,7 +34,7 @@ template <class R>
 struct AdjArgs {
   const R* lin;      // lambda_{t+1}
   R* lout;           // lambda_t
-  R* lrn;            // d/d rho^N: collide part, then total (fluid and extrapolated solid nodes)
+  R* lrn;            // d/d rho^N: the collide part at fluid nodes; d/d rho^N / den at extrapolated solids
   R* lnc;            // 3 planes: d/d n* from the collide (including its own curvature terms)
   R* lglen;          // d/d |G|
   R* lHn;            // per fluid id 4-vector (d/d H, n*): what the curvature transpose gathers
@@ -617,20 +618,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
 
 // ---------------------------------------------------------------------------------------------
 // Transpose of G(x) = 3 sum_i w_i c_i rho^N(x + c_i): d/d rho^N(y) gathers 3 w_i c_i . lG(y - c_i)
-// over fluid nodes y - c_i. EXT: y is a solid node with extrapolated colour, and what is stored is
+// over fluid nodes y - c_i. EXT: y is a solid node with extrapolated colour; k_adj_grad_ext stores
 // d/d rho^N(y) / den(y), den(y) = sum of w_k over the fluid nodes y + c_k (the extrapolation's
-// weight sum, the only form in which its transpose uses it); otherwise y is fluid and the collide
-// part of d/d rho^N is added.
+// weight sum, the only form in which its transpose uses it). For a fluid y, k_adj_colour adds
+// the sum to the collide part of d/d rho^N itself.
 // ---------------------------------------------------------------------------------------------
 template <int P, bool EXT>
-__global__ __launch_bounds__(kBlock) void k_adj_grad(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
+__device__ inline typename Prec<P>::R grad_transpose(const StepArgs<P>& A, const AdjArgs<typename Prec<P>::R>& J,
+                                                     int n, uint32_t inf, const Nbr& nb) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int t = logical_block() * kBlock + threadIdx.x;
-  if (t >= (EXT ? A.next : A.nfluid)) return;
-  const int n = EXT ? A.ext[t] : A.fluid[t];
-  const uint32_t inf = EXT ? A.einfo[t] : A.finfo[t];
-  const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
   // Every load is issued before any is used; a direction whose source is solid reads this
   // node's own entries and is discarded.
@@ -654,14 +651,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(StepArgs<P> A, AdjArgs<type
     if (D::cz[i]) v += R(D::cz[i]) * gz[i];
     s = src_fluid ? s + R(3.0 * D::w(i)) * v : s;
   }
-  if (EXT) {
-    R den = 0;  // > 0: a solid node on this list has a fluid neighbour
+  return s;
+}
+
+// The solid nodes with extrapolated colour (the fluid nodes' part is taken by k_adj_colour).
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adj_grad_ext(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  if (t >= A.next) return;
+  const int n = A.ext[t];
+  const uint32_t inf = A.einfo[t];
+  const Nbr nb = make_nbr(n, A.geo);
+  const R s = grad_transpose<P, true>(A, J, n, inf, nb);
+  R den = 0;  // > 0: a solid node on this list has a fluid neighbour
 #pragma unroll
-    for (int k = 0; k < 18; ++k) den = ((inf >> k) & 1u) ? den + R(D::w(k)) : den;
-    J.lrn[n] = s / den;
-  } else {
-    J.lrn[n] += s;
-  }
+  for (int k = 0; k < 18; ++k) den = ((inf >> k) & 1u) ? den + R(D::w(k)) : den;
+  J.lrn[n] = s / den;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -678,12 +685,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_colour(StepArgs<P> A, AdjArgs<ty
   const int n = A.fluid[t];
   const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
-  // At a solid y the adjoint is stored already divided by den(y) (k_adj_grad). Loads for all
+  // At a solid y the adjoint is stored already divided by den(y) (k_adj_grad_ext). Loads for all
   // directions first (a fluid z - c_j reads this node's own entry, discarded).
   R ly[18];
 #pragma unroll
   for (int j = 0; j < 18; ++j) ly[j] = J.lrn[((inf >> j) & 1u) ? nb.at(-D::cx[j], -D::cy[j], -D::cz[j]) : n];
-  R l = J.lrn[n];
+  // d/d rho^N of this fluid node: the collide part plus the gradient stencil's transpose
+  R l = J.lrn[n] + grad_transpose<P, false>(A, J, n, inf, nb);
 #pragma unroll
   for (int j = 0; j < 18; ++j) l = ((inf >> j) & 1u) ? l + R(D::w(j)) * ly[j] : l;  // z - c_j is solid
   const R rm = J.rmv[n];

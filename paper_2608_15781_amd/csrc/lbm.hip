@@ -667,8 +667,7 @@ lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* fields, co
   if (c->nb_fluid) {
     hipLaunchKernelGGL(k_adj_collide<P>, gf, block, 0, c->stream, A, J);
     hipLaunchKernelGGL(k_adj_normal<P>, gf, block, 0, c->stream, A, J);
-    hipLaunchKernelGGL((k_adj_grad<P, false>), gf, block, 0, c->stream, A, J);
-    if (c->nb_ext) hipLaunchKernelGGL((k_adj_grad<P, true>), ge, block, 0, c->stream, A, J);
+    if (c->nb_ext) hipLaunchKernelGGL(k_adj_grad_ext<P>, ge, block, 0, c->stream, A, J);
     hipLaunchKernelGGL(k_adj_colour<P>, gf, block, 0, c->stream, A, J);
     hipLaunchKernelGGL(k_adj_final<P>, gf, block, 0, c->stream, A, J);
   }
