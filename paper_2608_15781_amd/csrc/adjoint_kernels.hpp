@@ -9,8 +9,8 @@
 //   k_adj_collide   reverse of the collide kernel at each fluid node; the pull transposes to a
 //                   scatter that is a bijection on (node, direction), so every adjoint population
 //                   is written exactly once, without atomics (and the output needs no clearing;
-//                   the one entry without a reader, S_1 at an inlet facing an outflow node, is
-//                   zeroed by k_adj_final)
+//                   the two species entries without a reader, at the inlet and outflow planes,
+//                   are zeroed by k_adj_final)
 //   k_adj_normal    curvature transpose (gather of the neighbours' dH/dn*), then the normal and
 //                   Akai realignment reversed to d/dG; accumulates dL/dtheta
 //   k_adj_grad_ext  transpose of the isotropic gradient stencil (gather) at solid nodes
@@ -25,8 +25,8 @@
 
 namespace lbm {
 
-// Adjoint-state layout: 30 planes of N reals indexed by fluid id like the state (19 f^m, a,
-// v_x, v_y, v_z, 7 species).
+// Adjoint-state layout: 30 planes of reals, the state's plane stride apart and indexed by fluid
+// id like the state (19 f^m, a, v_x, v_y, v_z, 7 species).
 constexpr int kAdjPlanes = 30;
 constexpr int kAdjA = 19, kAdjV = 20, kAdjG = 23;
 

@@ -24,9 +24,9 @@
 // ((1 + rho^N)/2, (1 - rho^N)/2) is stored at full relative precision, the sign bit telling
 // which one it is. Colour densities and gradients of rho^N are formed from those directly.
 //
-// Layout: structure of arrays, one plane per population (planes a padded stride ps >= N apart),
-// fluid ids in node order (x fastest);
-// the colour scalars (a, v) as one 4-vector per fluid node. Two state buffers are used
+// Layout: structure of arrays, one plane per population, planes a padded stride ps (at least the
+// number of fluid nodes) apart, fluid ids in node order (x fastest); the colour scalars (a, v) as
+// one 4-vector per fluid node. Two state buffers are used
 // alternately (pull from one, write the other), so no kernel reads what another thread of the
 // same launch writes.
 //
