@@ -35,8 +35,8 @@ struct AdjArgs {
   const R* lin;      // lambda_{t+1}
   R* lout;           // lambda_t
   R* lrn;            // d/d rho^N: the collide part at fluid nodes; d/d rho^N / den at extrapolated solids
-  R* lnc;            // 3 planes: d/d n* from the collide (including its own curvature terms)
-  R* lglen;          // d/d |G|
+  R* lng;            // per fluid id 4-vector from the collide: d/d n* (including the node's own
+                     // curvature terms) and d/d |G|
   R* lHn;            // per fluid id 4-vector (d/d H, n*): what the curvature transpose gathers
   R* lG;             // 3 planes: d/d G
   R* lrr;            // d/d rho^r of the colour pass
@@ -520,10 +520,7 @@ __global__ __launch_bounds__(kBlock, P == 0 ? 1 : 3) void k_adj_collide(StepArgs
       J.lout[size_t(kAdjG + 6) * A.ps + t] = l_g[6];
     }
     J.lrn[n] = l_rn;
-    J.lnc[n] = l_n[0];
-    J.lnc[N + n] = l_n[1];
-    J.lnc[2 * N + n] = l_n[2];
-    J.lglen[n] = l_glen;
+    st4(J.lng, t, l_n[0], l_n[1], l_n[2], l_glen);
     st4(J.lHn, t, has_n ? l_H : R(0), nn[0], nn[1], nn[2]);
   }
   double s5[5] = {gxi, 0, 0, 0, 0};
@@ -551,13 +548,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
   // Every load of this node's own entries is issued here, before any is needed, so that they
   // share one memory round trip with the neighbours' ids (the wetting entries are read at every
   // node and used only at wetting nodes): the forward normal pass's n* and |G|, the normal
-  // before realignment, the wetting data, dL/d|G| and the running dL/dtheta.
+  // before realignment, the wetting data, dL/dn* and dL/d|G|, and the running dL/dtheta.
   const typename V4<R>::T nsv = ld4(A.nst, t);
   const typename V4<R>::T rv = ld4(A.nraw, t);
   const typename V4<R>::T wv = ld4(A.wet, t);
-  const R lgl = J.lglen[n];
+  const typename V4<R>::T lgv = ld4(J.lng, t);
+  const R lgl = lgv.w;
   const double gth0 = J.gtheta[n];
-  R mu[3] = {J.lnc[n], J.lnc[N + n], J.lnc[2 * N + n]};
+  R mu[3] = {lgv.x, lgv.y, lgv.z};
   // H(x) at each fluid neighbour x = y - c_i used n*(x + c_i) = n*(y):
   // dH(x)/dn*_a(y) = -3 w_i (c_ia - n_a(x) (n(x).c_i)). The fluid ids of all 18 neighbours
   // first, then one gather of (dL/dH, n*) each; a solid y - c_i reads this node's own entry

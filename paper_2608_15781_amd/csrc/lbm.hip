@@ -106,7 +106,7 @@ Layout make_layout(const lbm_params& p) {
 
 struct AdjLayout {
   size_t adj_bytes;                                                       // one adjoint state
-  size_t lrn, lnc, lglen, lHn, lG, lrr, lrm, lgo, rmv, nraw, partials, sum, total;  // scratch offsets
+  size_t lrn, lng, lHn, lG, lrr, lrm, lgo, rmv, nraw, partials, sum, total;  // scratch offsets
 };
 
 // Forward fields of one level, kept by lbm_step_fields for lbm_adjoint_step_fields: rho^N (dense),
@@ -136,8 +136,7 @@ AdjLayout make_adj_layout(const lbm_params& p) {
   A.adj_bytes = align_up(size_t(kAdjPlanes) * r * plane_stride(p));
   size_t o = 0;
   A.lrn = o; o = align_up(o + r * N);
-  A.lnc = o; o = align_up(o + 3 * r * N);
-  A.lglen = o; o = align_up(o + r * N);
+  A.lng = o; o = align_up(o + 4 * r * fluid_bound(p));
   A.lHn = o; o = align_up(o + 4 * r * fluid_bound(p));
   A.lG = o; o = align_up(o + 3 * r * N);
   A.lrr = o; o = align_up(o + r * N);
@@ -643,8 +642,7 @@ lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* fields, co
   J.lin = static_cast<const R*>(lin);
   J.lout = static_cast<R*>(lout);
   J.lrn = reinterpret_cast<R*>(sc + AL.lrn);
-  J.lnc = reinterpret_cast<R*>(sc + AL.lnc);
-  J.lglen = reinterpret_cast<R*>(sc + AL.lglen);
+  J.lng = reinterpret_cast<R*>(sc + AL.lng);
   J.lHn = reinterpret_cast<R*>(sc + AL.lHn);
   J.lG = reinterpret_cast<R*>(sc + AL.lG);
   J.lrr = reinterpret_cast<R*>(sc + AL.lrr);
