@@ -39,8 +39,8 @@ struct AdjArgs {
                      // curvature terms) and d/d |G|
   R* lHn;            // per fluid id 4-vector (d/d H, n*): what the curvature transpose gathers
   R* lG;             // 3 planes: d/d G
-  R* lrr;            // d/d rho^r of the colour pass
-  R* lrm;            // d/d rho^m of the colour pass
+  R* lr2;            // per node 2-vector (d/d rho^r, d/d rho^m) of the colour pass: read together,
+                     // one load per pull reader
   R* lgo;            // species outflow nodes: d/d S_1(x) through their own pull
   const R* rmv;      // rho^m of level t (forward recompute)
   double* gtheta;    // dL/dtheta per node (accumulated)
@@ -695,8 +695,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_colour(StepArgs<P> A, AdjArgs<ty
   const R rm = J.rmv[n];
   const R q = A.rhoN[n];
   const R one_plus_rn = signbit(q) ? R(2) + q : q;  // 1 + rho^N = 2 rho^r / rho^m
-  J.lrr[n] = R(2) * l / rm;
-  J.lrm[n] = -one_plus_rn * l / rm;
+  typename V2<R>::T v;
+  v.x = R(2) * l / rm;
+  v.y = -one_plus_rn * l / rm;
+  reinterpret_cast<typename V2<R>::T*>(J.lr2)[n] = v;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -721,7 +723,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_final(StepArgs<P> A, AdjArgs<typ
   for (int q = 0; q < 19; ++q) {
     const bool self = (q == 18) || ((inf >> D::opp[q]) & 1u);  // y + c_q solid: bounce-back reader
     const int rd = self ? n : nb.at(D::cx[q], D::cy[q], D::cz[q]);
-    const R lr = J.lrr[rd], lm = J.lrm[rd];
+    const typename V2<R>::T lv2 = reinterpret_cast<const typename V2<R>::T*>(J.lr2)[rd];
+    const R lr = lv2.x, lm = lv2.y;
     const R fq = Prec<P>::ld(A.fin[size_t(q) * A.ps + t], R(D::w(q)), A.inv_scale);
     J.lout[size_t(q) * A.ps + t] += lr * a + lm;
     la += lr * fq;

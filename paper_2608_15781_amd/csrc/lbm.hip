@@ -106,7 +106,7 @@ Layout make_layout(const lbm_params& p) {
 
 struct AdjLayout {
   size_t adj_bytes;                                                       // one adjoint state
-  size_t lrn, lng, lHn, lG, lrr, lrm, lgo, rmv, nraw, partials, sum, total;  // scratch offsets
+  size_t lrn, lng, lHn, lG, lr2, lgo, rmv, nraw, partials, sum, total;  // scratch offsets
 };
 
 // Forward fields of one level, kept by lbm_step_fields for lbm_adjoint_step_fields: rho^N (dense),
@@ -139,8 +139,7 @@ AdjLayout make_adj_layout(const lbm_params& p) {
   A.lng = o; o = align_up(o + 4 * r * fluid_bound(p));
   A.lHn = o; o = align_up(o + 4 * r * fluid_bound(p));
   A.lG = o; o = align_up(o + 3 * r * N);
-  A.lrr = o; o = align_up(o + r * N);
-  A.lrm = o; o = align_up(o + r * N);
+  A.lr2 = o; o = align_up(o + 2 * r * N);
   A.lgo = o; o = align_up(o + r * N);
   A.rmv = o; o = align_up(o + r * N);
   A.nraw = o; o = align_up(o + 4 * r * fluid_bound(p));
@@ -645,8 +644,7 @@ lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* fields, co
   J.lng = reinterpret_cast<R*>(sc + AL.lng);
   J.lHn = reinterpret_cast<R*>(sc + AL.lHn);
   J.lG = reinterpret_cast<R*>(sc + AL.lG);
-  J.lrr = reinterpret_cast<R*>(sc + AL.lrr);
-  J.lrm = reinterpret_cast<R*>(sc + AL.lrm);
+  J.lr2 = reinterpret_cast<R*>(sc + AL.lr2);
   J.lgo = reinterpret_cast<R*>(sc + AL.lgo);
   J.rmv = A.rm_out;
   J.gtheta = gth;

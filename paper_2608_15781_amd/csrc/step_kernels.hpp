@@ -56,6 +56,9 @@ constexpr int kXcd = 8;
 template <class R> struct V4;
 template <> struct V4<float> { using T = float4; };
 template <> struct V4<double> { using T = double4; };
+template <class R> struct V2;
+template <> struct V2<float> { using T = float2; };
+template <> struct V2<double> { using T = double2; };
 template <class R>
 __device__ inline typename V4<R>::T ld4(const R* p, size_t n) { return reinterpret_cast<const typename V4<R>::T*>(p)[n]; }
 template <class R>
