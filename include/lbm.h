@@ -62,7 +62,8 @@ typedef struct {
   int32_t nx, ny, nz;      /* lattice size, each >= 1, nx*ny*nz < 2^31 */
   int32_t precision;       /* lbm_precision */
   int32_t species;         /* 0: paper's model, reaction with C = 1; 1: D3Q7 species on */
-  int32_t x_open;          /* species only: inlet at x = 0 (C = c_inlet), outflow at x = nx-1 */
+  int32_t x_open;          /* species only: inlet at x = 0 (C = c_inlet), outflow at x = nx-1;
+                            * needs nx >= 2 */
   double tau;              /* relaxation time of the shear central moments, > 0.5 (eq. kinematic_viscosity) */
   double tau_species;      /* species BGK relaxation time, > 0.5 (D = (tau_species - 1/2)/4) */
   double sigma;            /* surface tension sigma >= 0 (eq. continuum_surface_force) */

@@ -205,6 +205,7 @@ lbm_status check_params(const lbm_params* p, char* msg, size_t len) {
     for (int a = 0; a < 3; ++a)
       if (!std::isfinite(p->accel[k][a])) { snprintf(msg, len, "accel must be finite"); return LBM_ERR_ARG; }
   if (p->species && p->x_open && (!std::isfinite(p->c_inlet) || p->c_inlet < 0)) { snprintf(msg, len, "c_inlet must be finite and >= 0"); return LBM_ERR_ARG; }
+  if (p->species && p->x_open && p->nx < 2) { snprintf(msg, len, "x_open needs nx >= 2 (inlet and outflow planes)"); return LBM_ERR_ARG; }
   if (p->precision == LBM_FP16_DEV && (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 20)) { snprintf(msg, len, "fp16_scale_log2 must be in 0..20"); return LBM_ERR_ARG; }
   if (p->fluid_nodes < 0 || double(p->fluid_nodes) > N) {
     snprintf(msg, len, "fluid_nodes must be in 0..nx*ny*nz");

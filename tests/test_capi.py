@@ -137,6 +137,18 @@ def test_largest_lattice_sizes(core):
     assert b"2^31" in core.lib().lbm_last_error(None)
 
 
+def test_open_species_planes_need_two_x_layers(core):
+    """With the species inlet and outflow planes on, nx = 1 would make them one plane: refused."""
+    b = ctypes.c_size_t()
+    p = core.make_params((1, 8, 8), precision="fp32", tau=0.8, species=True, x_open=True)
+    assert core.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == core.LBM_ERR_ARG
+    assert b"x_open" in core.lib().lbm_last_error(None)
+    for shape, kw in (((2, 8, 8), dict(species=True, x_open=True)), ((1, 8, 8), dict(species=True)),
+                      ((1, 8, 8), dict(x_open=True))):
+        p = core.make_params(shape, precision="fp32", tau=0.8, **kw)
+        assert core.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == 0
+
+
 def _init(core, p, N, ws_bytes, rho_r0=None, theta=None, ws_ptr=256):
     solid = np.zeros(N, np.uint8)
     rr = np.ones(N) if rho_r0 is None else rho_r0
