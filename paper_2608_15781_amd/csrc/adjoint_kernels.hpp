@@ -168,7 +168,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_adj_seed(StepArgs<P> A, typename Prec<P>::R* lout) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int t = logical_block() * kBlock + threadIdx.x;
+  const int t = fluid_tile(A) * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const size_t N = A.N;
   R a, b;
@@ -192,7 +192,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock, P == 0 ? 1 : 3) void k_adj_collide(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int t = logical_block() * kBlock + threadIdx.x;
+  const int t = fluid_tile(A) * kBlock + threadIdx.x;
   double gxi = 0.0;
   const int n = (t < A.nfluid) ? A.fluid[t] : 0;
   const uint32_t inf = (t < A.nfluid) ? A.finfo[t] : 0u;
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
     reduce_partials(J.partials, J.nparts, J.sum);
     if (threadIdx.x == 0) *J.gxi += J.sum[0];
   }
-  const int t = logical_block() * kBlock + threadIdx.x;
+  const int t = fluid_tile(A) * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
   const uint32_t inf = A.finfo[t];
@@ -678,7 +678,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_adj_colour(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int t = logical_block() * kBlock + threadIdx.x;
+  const int t = fluid_tile(A) * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
   const uint32_t inf = A.finfo[t];
@@ -710,7 +710,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_adj_final(StepArgs<P> A, AdjArgs<typename Prec<P>::R> J) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int t = logical_block() * kBlock + threadIdx.x;
+  const int t = fluid_tile(A) * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
   const uint32_t inf = A.finfo[t];

@@ -36,7 +36,7 @@ size_t store_bytes(int precision) { return precision == LBM_FP64 ? 8 : (precisio
 size_t real_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 
 struct Layout {
-  size_t info, wet, rhoN, nst, state[2], partials, ring, lists[2], linfo[2], fid, counts, total;
+  size_t info, wet, rhoN, nst, state[2], partials, ring, lists[2], linfo[2], fid, counts, order, total;
   size_t f_off, a_off, g_off, state_bytes;  // within one state buffer
   size_t ps;  // elements between consecutive state (and adjoint) planes
   int nblocks;  // one thread per node, rounded up to a multiple of kXcd workgroups
@@ -96,6 +96,7 @@ Layout make_layout(const lbm_params& p) {
   L.linfo[1] = o; o = align_up(o + 4 * E);
   L.fid = o; o = align_up(o + 4 * N);       // node -> fluid id
   L.counts = o; o = align_up(o + 4 * (size_t(nb) + 2));
+  L.order = o; o = align_up(o + 4 * size_t(nb));  // launch order of the fluid-list tiles
   L.state[0] = o; o = align_up(o + L.state_bytes);
   // The second state buffer comes last: lbm_init stages the host inputs there and in whatever
   // lies beyond it, so the workspace extends to the larger of the two.
@@ -161,6 +162,7 @@ struct lbm_ctx {
   int64_t steps;
   int nfluid, next;      // list lengths
   int nb_fluid, nb_ext;  // workgroups over each list (multiples of kXcd, 0 if empty)
+  bool ordered;          // fluid-list tiles launched in the order stored at L.order
   char err[512];
   // Profiling: 5 events per step of the current chunk (before colour, after each kernel).
   bool prof;
@@ -330,6 +332,12 @@ __global__ void k_flag_count(const uint32_t* info, int N, uint32_t mask, int* co
   if (threadIdx.x == 0) counts[blockIdx.x] = c;
 }
 
+// First node of each tile of kBlock consecutive fluid ids.
+__global__ void k_tile_heads(const int* fluid, int ntiles, int* heads) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < ntiles) heads[k] = fluid[size_t(k) * kBlock];
+}
+
 __global__ void k_gather_info(const uint32_t* info, const int* list, int len, uint32_t* out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < len) out[t] = info[list[t]];
@@ -413,6 +421,7 @@ StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
   A.ext = reinterpret_cast<const int*>(c->ws + L.lists[1]);
   A.einfo = reinterpret_cast<const uint32_t*>(c->ws + L.linfo[1]);
   A.fid = reinterpret_cast<const int*>(c->ws + L.fid);
+  A.order = c->ordered ? reinterpret_cast<const int*>(c->ws + L.order) : nullptr;
   A.next = c->next;
   A.info = reinterpret_cast<const uint32_t*>(c->ws + L.info);
   char* sb = c->ws + L.state[src_buf];
@@ -555,6 +564,40 @@ lbm_status launch_expand(lbm_ctx* c, void* fr, void* fp, void* g) {
   return LBM_OK;
 }
 
+// Launch order of the tiles of the fluid list. Tiles are keyed by their first node: y-bands of
+// kTileBand rows, each swept through z (x and y in order inside a band), and the XCD-aware
+// launch index walks that order, so each XCD takes whole bands and the tiles that read each
+// other's planes as neighbours run close together in time on one L2. With bands at least ny
+// rows deep the key is the node index, i.e. the list order itself, and no table is used.
+constexpr int kTileBand = 16;
+
+lbm_status build_tile_order(lbm_ctx* c) {
+  c->ordered = false;
+  const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
+  const int ntiles = (c->nfluid + kBlock - 1) / kBlock;
+  if (ntiles == 0 || kTileBand <= 0 || kTileBand >= ny) return LBM_OK;
+  int* d_order = reinterpret_cast<int*>(c->ws + c->L.order);
+  hipLaunchKernelGGL(k_tile_heads, dim3((ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream,
+                     reinterpret_cast<const int*>(c->ws + c->L.lists[0]), ntiles, d_order);
+  HIP_TRY(c, hipGetLastError());
+  std::vector<int> heads(ntiles);
+  HIP_TRY(c, hipMemcpyAsync(heads.data(), d_order, sizeof(int) * size_t(ntiles), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<int64_t> key(ntiles);
+  for (int k = 0; k < ntiles; ++k) {
+    const int64_t n = heads[k];
+    const int64_t x = n % nx, r = n / nx, y = r % ny, z = r / ny;
+    key[k] = (((y / kTileBand) * nz + z) * ny + y) * nx + x;
+  }
+  std::vector<int> order(c->nb_fluid);
+  for (int k = 0; k < c->nb_fluid; ++k) order[k] = k;  // the padding workgroups keep their index
+  std::stable_sort(order.begin(), order.begin() + ntiles, [&](int a, int b) { return key[a] < key[b]; });
+  HIP_TRY(c, hipMemcpyAsync(d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->ordered = true;
+  return LBM_OK;
+}
+
 template <int P>
 lbm_status launch_init(lbm_ctx* c, const uint8_t* d_solid, const uint8_t* d_react, const double* d_theta,
                        double theta_uniform, const double* d_rr, const double* d_rp, const double* d_c0) {
@@ -591,6 +634,7 @@ lbm_status launch_init(lbm_ctx* c, const uint8_t* d_solid, const uint8_t* d_reac
                          reinterpret_cast<uint32_t*>(c->ws + c->L.linfo[k]));
   c->nb_fluid = rounded_blocks(c->nfluid);
   c->nb_ext = rounded_blocks(c->next);
+  if (lbm_status s = build_tile_order(c); s != LBM_OK) return s;
   // The initial state goes into buffer 0 (make_args with src 1 writes buffer 0).
   StepArgs<P> A = make_args<P>(c, 1);
   if (c->nfluid > 0)

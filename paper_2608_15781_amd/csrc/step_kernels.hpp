@@ -119,6 +119,16 @@ __device__ inline int logical_block() {
   return (blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd;
 }
 
+// The tile of kBlock consecutive fluid ids that this workgroup processes: its XCD-aware launch
+// index, through the context's tile order when there is one (on large lattices the tiles are
+// launched in y-bands swept through z, so that tiles whose nodes neighbour each other across
+// planes are in flight on the same XCD and share its L2).
+template <class SA>
+__device__ inline int fluid_tile(const SA& A) {
+  const int lb = logical_block();
+  return A.order ? A.order[lb] : lb;
+}
+
 // Periodic neighbour offsets of one node.
 struct Nbr {
   int n, x;
@@ -173,6 +183,7 @@ struct StepArgs {
   const uint32_t* einfo;  // their info words
   int next;
   const int* fid;         // dense node -> fluid id (index into the state arrays), -1 for solid
+  const int* order;       // optional launch order of the fluid-list tiles (null: list order)
   const uint32_t* info;
   // state in (pull source) and out
   const S* fin;  // 19 planes f^m
@@ -259,7 +270,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int t = logical_block() * kBlock + threadIdx.x;
+  const int t = fluid_tile(A) * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
   const uint32_t inf = A.finfo[t];
@@ -334,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
   if (A.red_out && blockIdx.x == 0) reduce_partials(A.red_in, A.red_n, A.red_out);
-  const int t = logical_block() * kBlock + threadIdx.x;
+  const int t = fluid_tile(A) * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
   const uint32_t inf = A.finfo[t];
@@ -459,7 +470,7 @@ template <int P, bool MOM>
 __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
-  const int t = logical_block() * kBlock + threadIdx.x;
+  const int t = fluid_tile(A) * kBlock + threadIdx.x;
   double red5[5] = {0, 0, 0, 0, 0};
   const int n = (t < A.nfluid) ? A.fluid[t] : 0;
   const uint32_t inf = (t < A.nfluid) ? A.finfo[t] : 0u;
