@@ -567,15 +567,26 @@ lbm_status launch_expand(lbm_ctx* c, void* fr, void* fp, void* g) {
 // Launch order of the tiles of the fluid list. Tiles are keyed by their first node: y-bands of
 // kTileBand rows, each swept through z (x and y in order inside a band), and the XCD-aware
 // launch index walks that order, so each XCD takes whole bands and the tiles that read each
-// other's planes as neighbours run close together in time on one L2. With bands at least ny
-// rows deep the key is the node index, i.e. the list order itself, and no table is used.
+// other's planes as neighbours run close together in time on one L2. The plain list order
+// (each XCD a slab of whole planes) already keeps a tile's neighbours in the planes above and
+// below in L2 while three planes of per-node data fit in it; the bands are used only when they
+// do not (more than kOrderBytes, three quarters of one XCD's 4 MB L2). Measured: FP32 at 128^3
+// (3.3 MB by the count below), FP64 at 128^3 and every 512^3 case gain 2-4% with the bands; FP16
+// at 128^3 (2.1 MB) loses 3%.
+// With bands at least ny rows deep the key would be the node index, the list order itself.
 constexpr int kTileBand = 16;
+constexpr double kOrderBytes = 3.0 * (1 << 20);
 
 lbm_status build_tile_order(lbm_ctx* c) {
   c->ordered = false;
   const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
   const int ntiles = (c->nfluid + kBlock - 1) / kBlock;
   if (ntiles == 0 || kTileBand <= 0 || kTileBand >= ny) return LBM_OK;
+  // per fluid node: the state (19 + 7 stored populations, 4 colour scalars) and the normal
+  // pass's n* with |G| and rho^N
+  const double s = double(store_bytes(c->p.precision)), r = double(real_bytes(c->p.precision));
+  const double node_bytes = 26 * s + 4 * r + 5 * r;
+  if (3.0 * double(c->nfluid) / nz * node_bytes <= kOrderBytes) return LBM_OK;
   int* d_order = reinterpret_cast<int*>(c->ws + c->L.order);
   hipLaunchKernelGGL(k_tile_heads, dim3((ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream,
                      reinterpret_cast<const int*>(c->ws + c->L.lists[0]), ntiles, d_order);
