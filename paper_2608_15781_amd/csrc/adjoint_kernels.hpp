@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kBlock, P == 0 ? 1 : 3) void k_adj_collide(StepArgs
     int sid[18];
 #pragma unroll
     for (int i = 0; i < 18; ++i) {
-      sid[i] = ((inf >> i) & 1u) ? t : A.fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
+      sid[i] = ((inf >> i) & 1u) ? t : pull_source_id(A.fid, nb, t, i);
       sid_lds[i][threadIdx.x] = sid[i];
     }
     R f[19];
@@ -562,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
   // and is discarded.
   int mid[18];
 #pragma unroll
-  for (int i = 0; i < 18; ++i) mid[i] = A.fid[((inf >> i) & 1u) ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
+  for (int i = 0; i < 18; ++i) mid[i] = ((inf >> i) & 1u) ? t : pull_source_id(A.fid, nb, t, i);
 #pragma unroll
   for (int i = 0; i < 18; ++i) {
     const typename V4<R>::T qv = ld4(J.lHn, mid[i]);

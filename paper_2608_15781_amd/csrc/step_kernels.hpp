@@ -169,6 +169,16 @@ __device__ inline Nbr make_nbr(int n, const Geom& g) {
   return b;
 }
 
+// Fluid id of the pull source x - c_i of fluid node t, for a source that is fluid. Fluid ids are
+// ranks in dense order, so along x within a row (no periodic wrap) the source's id is t -+ 1 and
+// the id map is not read.
+__device__ inline int pull_source_id(const int* fid, const Nbr& nb, int t, int i) {
+  using D = D3Q19;
+  if (i == 0 && nb.dxm == -1) return t - 1;
+  if (i == 1 && nb.dxp == 1) return t + 1;
+  return fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
+}
+
 template <int P>
 struct StepArgs {
   using S = typename Prec<P>::S;
@@ -280,7 +290,8 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     const bool bb = (i < 18) && ((inf >> i) & 1u);
-    const int src = bb ? t : A.fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
+    // the rest population's source is the node itself: no lookup in the id map
+    const int src = (i == 18 || bb) ? t : pull_source_id(A.fid, nb, t, i);
     const int q = bb ? D::opp[i] : i;
     const R sgn = bb ? R(-1) : R(1);  // c_q = sgn * c_i
     const R fm = Prec<P>::ld(A.fin[size_t(q) * A.ps + src], R(D::w(i)), A.inv_scale);
@@ -482,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
     // and its neighbours' realigned normals), so that one memory round trip covers them.
     int sid[18];  // fluid ids of the pull sources (own id for bounce-back)
 #pragma unroll
-    for (int i = 0; i < 18; ++i) sid[i] = ((inf >> i) & 1u) ? t : A.fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
+    for (int i = 0; i < 18; ++i) sid[i] = ((inf >> i) & 1u) ? t : pull_source_id(A.fid, nb, t, i);
     R f[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
