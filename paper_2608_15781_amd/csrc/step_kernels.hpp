@@ -169,14 +169,42 @@ __device__ inline Nbr make_nbr(int n, const Geom& g) {
   return b;
 }
 
-// Fluid id of the pull source x - c_i of fluid node t, for a source that is fluid. Fluid ids are
-// ranks in dense order, so along x within a row (no periodic wrap) the source's id is t -+ 1 and
-// the id map is not read.
+// Fluid id of the pull source x - c_i of fluid node t, for a source that is fluid: t -+ 1 along
+// x within a row (fluid ids are ranks in dense order), else the id map's entry.
 __device__ inline int pull_source_id(const int* fid, const Nbr& nb, int t, int i) {
   using D = D3Q19;
   if (i == 0 && nb.dxm == -1) return t - 1;
   if (i == 1 && nb.dxp == 1) return t + 1;
   return fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
+}
+
+// Direction with no x component and the same y and z components as direction i (-1 for the
+// x axis, whose counterpart is the rest position).
+constexpr int yz_partner(int i) {
+  for (int j = 0; j < 18; ++j)
+    if (D3Q19::cx[j] == 0 && D3Q19::cy[j] == D3Q19::cy[i] && D3Q19::cz[j] == D3Q19::cz[i]) return j;
+  return -1;
+}
+
+// Fluid ids of the 18 pull sources x - c_i of fluid node t, the node's own id where the source is
+// solid. Fluid ids are ranks in dense order, so two fluid nodes next to each other along x within
+// a row (no periodic wrap) have ids one apart: a source x - c_i with c_ix != 0 takes the id of its
+// partner (x, y - c_iy, z - c_iz) minus c_ix when the partner is fluid, and the id map is read only
+// for the other sources.
+__device__ inline void pull_sources(const int* fid, const Nbr& nb, int t, uint32_t inf, int sid[18]) {
+  using D = D3Q19;
+#pragma unroll
+  for (int i = 0; i < 18; ++i)
+    if (D::cx[i] == 0) sid[i] = ((inf >> i) & 1u) ? t : fid[nb.at(0, -D::cy[i], -D::cz[i])];
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    if (D::cx[i] == 0) continue;
+    const int m = yz_partner(i);
+    const int mid = (m < 0) ? t : sid[m];
+    const bool mfluid = (m < 0) || !((inf >> m) & 1u);
+    const bool in_row = (D::cx[i] > 0) ? (nb.dxm == -1) : (nb.dxp == 1);
+    sid[i] = ((inf >> i) & 1u) ? t : ((mfluid && in_row) ? mid - D::cx[i] : fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])]);
+  }
 }
 
 template <int P>
@@ -286,12 +314,13 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
   const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
   const size_t N = A.N;
+  int sid[18];
+  pull_sources(A.fid, nb, t, inf, sid);
   R rm = 0, rr = 0, rp = 0;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     const bool bb = (i < 18) && ((inf >> i) & 1u);
-    // the rest population's source is the node itself: no lookup in the id map
-    const int src = (i == 18 || bb) ? t : pull_source_id(A.fid, nb, t, i);
+    const int src = (i == 18) ? t : sid[i];
     const int q = bb ? D::opp[i] : i;
     const R sgn = bb ? R(-1) : R(1);  // c_q = sgn * c_i
     const R fm = Prec<P>::ld(A.fin[size_t(q) * A.ps + src], R(D::w(i)), A.inv_scale);
@@ -491,7 +520,11 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
     const size_t N = A.N;
     // All loads of the node first (pull of f^m and g with halfway bounce-back, rho^N, the node's
     // and its neighbours' realigned normals), so that one memory round trip covers them.
-    int sid[18];  // fluid ids of the pull sources (own id for bounce-back)
+    // Fluid ids of the pull sources (own id for bounce-back). Here every id but the row's
+    // neighbours comes from the id map: the partner-derived ids of pull_sources made this pass 6%
+    // slower (its loads then issue in dependent batches), while they halve the colour pass's
+    // registers.
+    int sid[18];
 #pragma unroll
     for (int i = 0; i < 18; ++i) sid[i] = ((inf >> i) & 1u) ? t : pull_source_id(A.fid, nb, t, i);
     R f[19];
