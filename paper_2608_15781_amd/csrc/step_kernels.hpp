@@ -302,7 +302,9 @@ __global__ __launch_bounds__(kBlock) void k_finish_reduce(const double* partials
 }
 
 // ---------------------------------------------------------------------------------------------
-// colour: rho^N = (rho^r - rho^p)/rho^m from the pulled populations.
+// colour: rho^N = (rho^r - rho^p)/rho^m from the pulled populations. The pull-source ids come
+// from pull_sources (most of them derived from a neighbour's rank), which keeps the pass at 56
+// VGPRs and eight waves per SIMD; the pass is bound by its gathers, not by its bytes.
 // ---------------------------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
