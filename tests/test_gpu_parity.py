@@ -146,6 +146,26 @@ def test_ragged_shape_fp64(core, oracle_mod):
     _compare(gpu, ref, FP64_TOL, "ragged 19x13x11")
 
 
+@pytest.mark.parametrize("nx", [1, 2, 3])
+def test_thin_x_lattices_fp64(core, oracle_mod, nx):
+    """Lattices one, two and three nodes wide in x with scattered solids, every feature on. Along
+    x a row's pull sources wrap onto the node itself (nx = 1) or onto its other neighbour
+    (nx = 2), so the kernels' source ids taken from a row neighbour's fluid id, or from the
+    y/z partner's, must fall back to the id map exactly there."""
+    shape = (nx, 9, 7)
+    rng = np.random.default_rng(40 + nx)
+    solid = (rng.uniform(size=(7, 9, nx)) < 0.3).astype(np.uint8)
+    theta = np.deg2rad(rng.uniform(40, 140, solid.shape))
+    rr0 = (1 - solid) * (rng.uniform(size=solid.shape) > 0.5)
+    rp0 = (1 - solid) - rr0
+    kw = dict(FULL_KW, x_open=nx >= 2)
+    gpu, ref = _pair(core, oracle_mod, shape, solid=solid, theta=theta, rho_r0=rr0.astype(float),
+                     rho_p0=rp0.astype(float), precision="fp64", **kw)
+    gpu.step(30)
+    ref.step(30)
+    _compare(gpu, ref, FP64_TOL, "thin x nx=%d" % nx)
+
+
 def test_quasi_2d_contact_line_fp64(core, oracle_mod):
     """ny = 1 (periodic neighbours wrap onto the node itself): a cap on a wall."""
     nx, nz = 40, 24
