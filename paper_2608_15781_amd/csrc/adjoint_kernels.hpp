@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kBlock, P == 0 ? 1 : 3) void k_adj_collide(StepArgs
     // The pull sources are needed again by the final scatter; they wait in LDS meanwhile.
     __shared__ int sid_lds[18][kBlock];
     int sid[18];
-    pull_sources(A.fid, nb, t, inf, sid);
+    pull_sources_lean(A.fid, nb, t, inf, sid);
 #pragma unroll
     for (int i = 0; i < 18; ++i) sid_lds[i][threadIdx.x] = sid[i];
     R f[19];
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_normal(StepArgs<P> A, AdjArgs<ty
   // first, then one gather of (dL/dH, n*) each; a solid y - c_i reads this node's own entry
   // and is discarded.
   int mid[18];
-  pull_sources(A.fid, nb, t, inf, mid);
+  pull_sources_lean(A.fid, nb, t, inf, mid);
 #pragma unroll
   for (int i = 0; i < 18; ++i) {
     const typename V4<R>::T qv = ld4(J.lHn, mid[i]);

@@ -169,15 +169,6 @@ __device__ inline Nbr make_nbr(int n, const Geom& g) {
   return b;
 }
 
-// Fluid id of the pull source x - c_i of fluid node t, for a source that is fluid: t -+ 1 along
-// x within a row (fluid ids are ranks in dense order), else the id map's entry.
-__device__ inline int pull_source_id(const int* fid, const Nbr& nb, int t, int i) {
-  using D = D3Q19;
-  if (i == 0 && nb.dxm == -1) return t - 1;
-  if (i == 1 && nb.dxp == 1) return t + 1;
-  return fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
-}
-
 // Direction with no x component and the same y and z components as direction i (-1 for the
 // x axis, whose counterpart is the rest position).
 constexpr int yz_partner(int i) {
@@ -190,8 +181,42 @@ constexpr int yz_partner(int i) {
 // solid. Fluid ids are ranks in dense order, so two fluid nodes next to each other along x within
 // a row (no periodic wrap) have ids one apart: a source x - c_i with c_ix != 0 takes the id of its
 // partner (x, y - c_iy, z - c_iz) minus c_ix when the partner is fluid, and the id map is read only
-// for the other sources.
+// for the other sources. All of those reads are issued before any id is formed, so they are in
+// flight together.
 __device__ inline void pull_sources(const int* fid, const Nbr& nb, int t, uint32_t inf, int sid[18]) {
+  using D = D3Q19;
+  // Which ids follow from a neighbour's: known from the info bits alone, before any load.
+  bool derived[18];
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    const int m = yz_partner(i);
+    const bool mfluid = (m < 0) || !((inf >> m) & 1u);
+    const bool in_row = (D::cx[i] > 0) ? (nb.dxm == -1) : (nb.dxp == 1);
+    derived[i] = (D::cx[i] != 0) && mfluid && in_row;
+  }
+  // Every id-map read first, so that they are in flight together; only then the ids.
+  int look[18];
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    look[i] = 0;
+    if (!((inf >> i) & 1u) && !derived[i]) look[i] = fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])];
+  }
+#pragma unroll
+  for (int i = 0; i < 18; ++i)
+    if (D::cx[i] == 0) sid[i] = ((inf >> i) & 1u) ? t : look[i];
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    if (D::cx[i] == 0) continue;
+    const int m = yz_partner(i);
+    const int mid = (m < 0) ? t : sid[m];
+    sid[i] = ((inf >> i) & 1u) ? t : (derived[i] ? mid - D::cx[i] : look[i]);
+  }
+}
+
+// The same ids with fewer registers live: each id-map read is consumed as it arrives, so the reads
+// are not all in flight at once. For the adjoint passes, whose other state leaves few registers
+// (the batched form made them spill or lose a wave per SIMD).
+__device__ inline void pull_sources_lean(const int* fid, const Nbr& nb, int t, uint32_t inf, int sid[18]) {
   using D = D3Q19;
 #pragma unroll
   for (int i = 0; i < 18; ++i)
@@ -303,8 +328,8 @@ __global__ __launch_bounds__(kBlock) void k_finish_reduce(const double* partials
 
 // ---------------------------------------------------------------------------------------------
 // colour: rho^N = (rho^r - rho^p)/rho^m from the pulled populations. The pull-source ids come
-// from pull_sources (most of them derived from a neighbour's rank), which keeps the pass at 56
-// VGPRs and eight waves per SIMD; the pass is bound by its gathers, not by its bytes.
+// from pull_sources (most of them derived from a neighbour's rank); the pass then fits in 60
+// VGPRs and eight waves per SIMD, and is bound by its gathers, not by its bytes.
 // ---------------------------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
@@ -528,13 +553,8 @@ __global__ __launch_bounds__(kBlock, P >= 2 ? 5 : 1) void k_collide(StepArgs<P> 
     const size_t N = A.N;
     // All loads of the node first (pull of f^m and g with halfway bounce-back, rho^N, the node's
     // and its neighbours' realigned normals), so that one memory round trip covers them.
-    // Fluid ids of the pull sources (own id for bounce-back). Here every id but the row's
-    // neighbours comes from the id map: the partner-derived ids of pull_sources made this pass 6%
-    // slower (its loads then issue in dependent batches), while they halve the colour pass's
-    // registers.
-    int sid[18];
-#pragma unroll
-    for (int i = 0; i < 18; ++i) sid[i] = ((inf >> i) & 1u) ? t : pull_source_id(A.fid, nb, t, i);
+    int sid[18];  // fluid ids of the pull sources (own id for bounce-back)
+    pull_sources(A.fid, nb, t, inf, sid);
     R f[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
