@@ -173,6 +173,34 @@ def test_gradient_matches_oracle_duals_and_checkpointing(core, oracle_mod):
     assert np.array_equal(th_k.grad.numpy().ravel(), g) and float(xi_k.grad) == float(gxi)
 
 
+@pytest.mark.parametrize("nx", [1, 2])
+def test_thin_x_gradient_against_oracle_duals(core, oracle_mod, nx):
+    """Lattices one and two nodes wide in x with scattered solids: the adjoint passes take the
+    pull-source ids from a row neighbour's or a y/z partner's fluid id, which must fall back to
+    the id map where a row wraps onto the node itself or onto its other neighbour."""
+    from paper_2608_15781_amd import autograd as ag
+
+    shape, xi, T = (nx, 9, 8), 0.05, 15
+    rng = np.random.default_rng(60 + nx)
+    solid = (rng.uniform(size=(8, 9, nx)) < 0.3).astype(np.uint8)
+    theta = np.deg2rad(rng.uniform(60, 120, solid.shape))
+    rr0 = ((1 - solid) * (rng.uniform(size=solid.shape) > 0.5)).astype(float)
+    rp0 = (1 - solid) - rr0
+    d1 = rng.normal(size=solid.shape) * (1 - solid)
+    kw = dict(KW, x_open=nx >= 2)
+    L, dL = oracle_mod.grad(shape, solid, theta, xi, T, dtheta=[d1.ravel(), np.zeros(solid.size)], dxi=[0.0, 1.0],
+                            rho_r0=rr0, rho_p0=rp0, tau_c=0.8, **kw)
+    sim = core.Lbm(shape, solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, xi=xi, precision="fp64",
+                   tau_species=0.8, **kw)
+    Lg, cps, final = ag.forward_states(sim, T, 5)
+    gth, gxi, _ = ag.adjoint_gradients(sim, T, 5, cps, final)
+    ad = [float(gth.cpu().numpy() @ d1.ravel()), float(gxi)]
+    print("nx=%d L gpu %.12e oracle %.12e; dL adjoint %s oracle duals %s" % (nx, Lg, L, ad, list(dL)), flush=True)
+    assert abs(Lg - L) < 1e-10 * abs(L)
+    for a, b in zip(ad, dL):
+        assert abs(a - b) < 1e-8 * abs(b) + 1e-14, (a, b)
+
+
 def test_contact_angle_gradient_finite_differences_on_wall_nodes(core):
     from paper_2608_15781_amd import autograd as ag
 
