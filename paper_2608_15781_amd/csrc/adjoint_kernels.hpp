@@ -170,7 +170,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(StepArgs<P> A, typename Pre
   using D = D3Q19;
   const int t = fluid_tile(A) * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
-  const size_t N = A.N;
   R a, b;
   unpack_frac(ld4(A.ain, t).x, a, b);
   R s = 0;
@@ -198,7 +197,6 @@ __global__ __launch_bounds__(kBlock, P == 0 ? 1 : 3) void k_adj_collide(StepArgs
   const uint32_t inf = (t < A.nfluid) ? A.finfo[t] : 0u;
   if (inf & kFluid) {
     const Nbr nb = make_nbr(n, A.geo);
-    const size_t N = A.N;
     // ---------------- forward recompute ----------------
     // The pull sources are needed again by the final scatter; they wait in LDS meanwhile.
     __shared__ int sid_lds[18][kBlock];
@@ -712,7 +710,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_final(StepArgs<P> A, AdjArgs<typ
   const int n = A.fluid[t];
   const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
-  const size_t N = A.N;
   R a, b;
   unpack_frac(ld4(A.ain, t).x, a, b);
   R la = 0, lv[3] = {0, 0, 0};

@@ -314,7 +314,6 @@ __global__ void k_init_state(StepArgs<P> A, const double* rr0, const double* rp0
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
-  const size_t N = A.N;
   const double rm = rr0[n] + rp0[n];
   for (int i = 0; i < 19; ++i) A.fout[size_t(i) * A.ps + t] = Prec<P>::st(R(D::w(i) * rm), R(D::w(i)), A.scale);
   st4(A.aout, t, R(pack_frac(rr0[n] / rm, rp0[n] / rm)), R(0), R(0), R(0));

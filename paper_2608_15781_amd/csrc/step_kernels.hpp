@@ -340,7 +340,6 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
   const int n = A.fluid[t];
   const uint32_t inf = A.finfo[t];
   const Nbr nb = make_nbr(n, A.geo);
-  const size_t N = A.N;
   int sid[18];
   pull_sources(A.fid, nb, t, inf, sid);
   R rm = 0, rr = 0, rp = 0;
