@@ -12,6 +12,8 @@ device copy of a known size (``--copy-mib``), whose counter readings calibrate t
 ``python3 -m paper_2608_15781_amd.profile_run report --precision P --fluid-nodes F TRACE FETCH WRITE``
 turns the three CSV folders into the short markdown summary kept under ``profiles/``;
 ``profile_run bench-trace TRACE BENCH_JSON`` summarises a kernel trace of bench.py itself.
+``profile_run counters PASS_A PASS_B`` summarises two hardware-counter runs (the counter sets of
+COUNTER_PASSES, one run each) into what bounds each step kernel.
 """
 from __future__ import annotations
 
@@ -240,6 +242,80 @@ def bench_trace(args):
     print("\n".join(lines))
 
 
+# Two counter sets, each within one run's per-block limits (8 SQ; 2 TA, 4 TCP, 2 TCC).
+COUNTER_PASSES = (
+    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VMEM SQ_INST_LEVEL_VMEM "
+    "SQ_INSTS_VMEM_RD SQ_LEVEL_WAVES",
+    "TA_TA_BUSY TA_ADDR_STALLED_BY_TC_CYCLES TCP_PENDING_STALL_CYCLES TCP_TCC_READ_REQ "
+    "TCP_READ_TAGCONFLICT_STALL_CYCLES TCP_PERF_SEL_TOTAL_READ TCC_HIT TCC_MISS",
+)
+CLOCK_HZ = 2.4e9  # MI355X peak engine clock
+N_CU = 256        # one texture-address unit per compute unit
+
+
+def _counters_per_kernel(out_dir):
+    """Per kernel: dispatch count, mean duration (the counter run's own timestamps) and the mean
+    of each counter per dispatch (summed over the counter's hardware instances)."""
+    disp = {}
+    for r in _rows(os.path.join(out_dir, "**", "*counter_collection.csv")):
+        d = disp.setdefault(int(r["Dispatch_Id"]), dict(
+            name=_short(r["Kernel_Name"]), dur=(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9, c={}))
+        d["c"][r["Counter_Name"]] = d["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    agg = {}
+    for d in disp.values():
+        a = agg.setdefault(d["name"], dict(n=0, dur=0.0, c={}))
+        a["n"] += 1
+        a["dur"] += d["dur"]
+        for k, v in d["c"].items():
+            a["c"][k] = a["c"].get(k, 0.0) + v
+    return {k: dict(n=a["n"], dur=a["dur"] / a["n"], c={c: v / a["n"] for c, v in a["c"].items()})
+            for k, a in agg.items()}
+
+
+def counters(args):
+    """Markdown summary of the two hardware-counter runs of COUNTER_PASSES."""
+    sys.path.insert(0, ROOT)
+    from paper_2608_15781_amd import build
+
+    pa, pb = _counters_per_kernel(args.out), _counters_per_kernel(args.fetch)
+    lines = ["# Hardware counters of the step kernels, %s, %s storage" % (args.workload, args.precision), "",
+             "Commands (repository root, `cd /tmp && export TMPDIR=/tmp` first, `PYTHONPATH` = repository root):", "",
+             "```"]
+    for k, ctrs in enumerate(COUNTER_PASSES):
+        lines.append("rocprofv3 --pmc %s --output-format csv -d OUT/pass%s -o run -- python3 -m "
+                     "paper_2608_15781_amd.profile_run --precision %s --steps %d"
+                     % (ctrs, "AB"[k], args.precision, args.steps))
+    lines += ["python3 -m paper_2608_15781_amd.profile_run counters --precision %s OUT/passA OUT/passB"
+              % args.precision, "```", "",
+              "| kernel | dispatches | us (counter run) | TA busy | TA stalled on L2 | L2 hit | VMEM reads per wave |",
+              "|---|---|---|---|---|---|---|"]
+
+    def pct(x):
+        return "%.0f%%" % (100 * x)
+
+    for name in sorted(pb, key=lambda k: -pb[k]["dur"]):
+        if not name.startswith("lbm::k_"):
+            continue
+        b, a = pb[name], pa.get(name)
+        ta = b["c"].get("TA_TA_BUSY", 0.0)
+        busy = ta / (b["dur"] * CLOCK_HZ * N_CU) if b["dur"] > 0 else 0.0
+        stalled = b["c"].get("TA_ADDR_STALLED_BY_TC_CYCLES", 0.0) / ta if ta else 0.0
+        hit, miss = b["c"].get("TCC_HIT", 0.0), b["c"].get("TCC_MISS", 0.0)
+        l2 = hit / (hit + miss) if hit + miss else 0.0
+        rd = "-"
+        if a and a["c"].get("SQ_WAVES"):
+            rd = "%.1f" % (a["c"].get("SQ_INSTS_VMEM_RD", 0.0) / a["c"]["SQ_WAVES"])
+        lines.append("| `%s` | %d | %.2f | %s | %s | %s | %s |"
+                     % (name, b["n"], b["dur"] * 1e6, pct(busy), pct(stalled), pct(l2), rd))
+    lines += ["", "TA busy = TA_TA_BUSY / (duration x %.1f GHz x %d units): the share of the texture-address "
+              "units' cycles spent processing vector-memory addresses (gathers, loads and stores); TA stalled on "
+              "L2 = TA_ADDR_STALLED_BY_TC_CYCLES / TA_TA_BUSY; L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS); VMEM reads "
+              "per wave = SQ_INSTS_VMEM_RD / SQ_WAVES. Counter runs serialise the dispatches, so their durations read somewhat above the kernel trace's."
+              % (CLOCK_HZ / 1e9, N_CU), "",
+              "- source_digest: %s" % build.source_digest()]
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", nargs="?", default="run")
@@ -263,6 +339,8 @@ def main():
         run_adjoint(args)
     elif args.cmd == "bench-trace":
         bench_trace(args)
+    elif args.cmd == "counters":
+        counters(args)
     else:
         run(args)
 
