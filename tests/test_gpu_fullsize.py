@@ -1,7 +1,7 @@
 """The large workloads at full size, on sampled nodes the oracle computes one by one.
 
 256^3 (wavelength 16, seed 3) in FP64 and 512^3 (wavelength 32, porosity 0.55, theta 30 deg) in
-FP32 storage, in the launch configuration of the library's step. After a few steps the GPU's
+FP32 and FP16 storage, in the launch configuration of the library's step. After a few steps the GPU's
 populations around each sampled node are cut out (a 13^3 box, periodic indexing), the oracle is
 started from them on a 13^3 periodic domain with the same mask and contact angles, and both take
 one step. The post-collision populations of the sampled node after that step depend on the state
@@ -122,3 +122,11 @@ def test_bijel256_fp64_sampled_against_oracle(core, oracle_mod):
 def test_bijel512_fp32_sampled_against_oracle(core, oracle_mod):
     # the oracle steps the FP32 state exactly (FP64); the GPU rounds to FP32 once
     _run(core, oracle_mod, "bijel512", "fp32", warm=5, tol_pop=1e-6, tol_rho=2e-6)
+
+
+def test_bijel512_fp16_sampled_against_oracle(core, oracle_mod):
+    # FP16 deviation storage, the configuration compared with FP32 at 512^3: the GPU rounds each
+    # stored deviation to half precision (at most 2^-12 of it after the 2^12 scaling); species
+    # deviations reach 0.25 (C between 0 and 1), so a population is off by at most 6.1e-5 plus
+    # FP32 arithmetic, and a density (at most 7 such terms for C) by at most 4.3e-4
+    _run(core, oracle_mod, "bijel512", "fp16", warm=5, tol_pop=1e-4, tol_rho=5e-4)
