@@ -1,8 +1,8 @@
 """The large workloads at full size, on sampled nodes the oracle computes one by one.
 
-256^3 (wavelength 16, seed 3) in FP64 and 512^3 (wavelength 32, porosity 0.55, theta 30 deg) in
-FP32 and FP16 storage, in the launch configuration of the library's step. After a few steps the GPU's
-populations around each sampled node are cut out (a 13^3 box, periodic indexing), the oracle is
+256^3 (wavelength 16, seed 3) in FP64, FP16 and BF16 and 512^3 (wavelength 32, porosity 0.55,
+theta 30 deg) in FP32 and FP16 storage, in the launch configuration of the library's step. After
+a few steps the GPU's populations around each sampled node are cut out (a 13^3 box, periodic indexing), the oracle is
 started from them on a 13^3 periodic domain with the same mask and contact angles, and both take
 one step. The post-collision populations of the sampled node after that step depend on the state
 within 4 nodes and on the mask within 4 nodes (solid normal, extrapolated colour), and the
@@ -117,6 +117,17 @@ def _run(core, oracle_mod, name, precision, warm, tol_pop, tol_rho):
 
 def test_bijel256_fp64_sampled_against_oracle(core, oracle_mod):
     _run(core, oracle_mod, "bijel256", "fp64", warm=5, tol_pop=1e-12, tol_rho=1e-12)
+
+
+@pytest.mark.parametrize("precision,tol_pop,tol_rho", [
+    # half precision: at most 2^-12 of a deviation (species deviations reach 0.25): 6.1e-5 per
+    # population, 4.3e-4 for a sum of 7
+    ("fp16", 1e-4, 5e-4),
+    # bfloat16: at most 2^-8 of a deviation: 9.8e-4 per population, 6.8e-3 for a sum of 7
+    ("bf16", 2e-3, 1e-2),
+])
+def test_bijel256_reduced_storage_sampled_against_oracle(core, oracle_mod, precision, tol_pop, tol_rho):
+    _run(core, oracle_mod, "bijel256", precision, warm=5, tol_pop=tol_pop, tol_rho=tol_rho)
 
 
 def test_bijel512_fp32_sampled_against_oracle(core, oracle_mod):
