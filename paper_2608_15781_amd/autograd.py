@@ -4,9 +4,10 @@ GasProduction.apply(theta, xi, problem) runs the lattice Boltzmann step ``proble
 times from the problem's initial state and returns L = m^p(T) - m^p(0), the product (gas) mass
 created, as a float64 scalar tensor. Its backward pass is the hand-written discrete adjoint of
 the library (lbm_adjoint_seed / lbm_adjoint_step) with checkpoint-and-recompute over time: the
-forward pass keeps the state every ``problem["checkpoint"]`` steps; the backward pass restores
-each checkpoint in reverse order, recomputes that segment's states, and runs the adjoint steps
-backwards through it. Memory: one state per checkpoint plus one segment of states.
+forward pass keeps the state every ``problem["checkpoint"]`` steps, and the last segment whole;
+the backward pass runs the adjoint steps backwards through that segment, then restores each
+earlier checkpoint in reverse order, recomputes that segment's states, and runs the adjoint steps
+backwards through it. Memory: one state per checkpoint plus one segment of states and fields.
 ``problem["checkpoint"] = 0`` keeps every level instead (state and forward fields, written
 straight into buffers of their own by the forward pass), and the backward pass recomputes
 nothing: faster, for T levels of memory.
@@ -32,19 +33,37 @@ def _build(theta, xi, problem):
                     device=problem.get("device", "cuda:0"), **kw)
 
 
+class Checkpoints(dict):
+    """States at the checkpoint levels, {t: state}. `last` is the last segment as the forward pass
+    kept it: (s0, [state of each level s0 .. T-1], [the fields of those levels])."""
+    last = None
+
+
 def forward_states(sim, steps, checkpoint):
-    """Runs `steps` steps; returns (L, checkpoints {t: state}, final state)."""
-    cps = {0: sim.get_state()}
-    conv = 0.0
+    """Runs `steps` steps; returns (L, checkpoints, final state) with L = m^p(T) - m^p(0). The
+    last segment goes from buffer to buffer keeping every level's state and fields
+    (lbm_step_from), so the reverse sweep, which starts there, need not recompute it."""
+    mp0 = _product_mass(sim)
+    t0 = sim.steps_done
+    cps = Checkpoints({0: sim.get_state()})
+    s_last = (steps - 1) // checkpoint * checkpoint if steps > 0 else 0
     t = 0
-    while t < steps:
-        n = min(checkpoint, steps - t)
-        red = sim.step(n)
-        conv += float(red[:, 2].sum())
+    while t < s_last:
+        n = min(checkpoint, s_last - t)
+        sim.step(n)
         t += n
-        if t < steps:
-            cps[t] = sim.get_state()
-    return conv, cps, sim.get_state()
+        cps[t] = sim.get_state()
+    if steps > 0:
+        n = steps - s_last
+        states = [cps[s_last]] + [sim.new_state() for _ in range(n)]
+        fields = [sim.new_fields() for _ in range(n)]
+        sim.step_chain(states, fields)
+        final = states.pop()
+        sim.set_state(final, t0 + steps)
+        cps.last = (s_last, states, fields)
+    else:
+        final = sim.get_state()
+    return _product_mass(sim) - mp0, cps, final
 
 
 def _product_mass(sim):
@@ -96,21 +115,34 @@ def adjoint_gradients(sim, steps, checkpoint, cps, final_state, keep_fields=True
     (lbm_step_from): the checkpoint itself is level s0 and every later level is written straight
     into a buffer of its own, so no state is copied. With keep_fields the recomputation also keeps
     every level's rho^N, n* and rho^m, which the adjoint steps then reuse instead of recomputing
-    (same values bit for bit). Memory: `checkpoint` state buffers, plus as many field buffers."""
+    (same values bit for bit). The last segment, when the forward pass kept it (forward_states),
+    is not recomputed. Memory: `checkpoint` state buffers, plus as many field buffers."""
     dev = sim.device
     lam = sim.new_adjoint()
     lam2 = sim.new_adjoint()
     scratch = sim.new_scratch()
     gth = torch.zeros(sim.N, dtype=torch.float64, device=dev)
     gxi = torch.zeros(1, dtype=torch.float64, device=dev)
-    fields = [sim.new_fields() for _ in range(checkpoint)] if keep_fields else None
-    # bufs[k] holds level s0 + k (k >= 1); bufs[0] takes the output of the segment's last step,
-    # which is only run for its fields
-    bufs = [sim.new_state() for _ in range(checkpoint)]
+    kept = getattr(cps, "last", None)
+    bufs = fields = None
     sim.adjoint_seed(final_state, lam)
     starts = sorted(cps)
     for s0 in reversed(starts):
         s1 = min(s0 + checkpoint, steps)
+        if kept is not None and s0 == kept[0]:
+            # kept whole by the forward pass: no recomputation (and the caller's buffers stay as
+            # they are, so the sweep can be run again)
+            seg, segf = kept[1], kept[2]
+            for t in range(s1 - 1, s0 - 1, -1):
+                sim.adjoint_step(seg[t - s0], lam, lam2, scratch, gth, gxi, fields=segf[t - s0])
+                lam, lam2 = lam2, lam
+            continue
+        if bufs is None:
+            # bufs[k] holds level s0 + k (k >= 1); bufs[0] takes the output of the segment's last
+            # step, which is only run for its fields
+            bufs = [sim.new_state() for _ in range(checkpoint)]
+            if keep_fields:
+                fields = [sim.new_fields() for _ in range(checkpoint)]
         seg = [cps[s0]] + bufs[1:s1 - s0]
         for t in range(s0, s1):
             k = t - s0
