@@ -205,10 +205,12 @@ lbm_status lbm_step_fields(lbm_ctx* ctx, void* d_fields);
  * of lbm_get_state. The context's own state and step count are left as they are; its geometry,
  * parameters and per-step workspace fields are used. d_fields: NULL, or a buffer of
  * lbm_fields_bytes that receives the level-t fields of d_src as lbm_step_fields writes them.
- * Enqueued only, like lbm_step_async: no reductions, no non-finite report. Results are bitwise
- * those of lbm_step from the same state. For checkpoint recomputation that keeps every level
- * without copying states. Errors: LBM_ERR_ARG for NULL states or overlapping buffers,
- * LBM_ERR_HIP. */
+ * d_dst may be NULL when d_fields is not: then only the fields are computed (the colour,
+ * extrapolation and normal passes; no collision, no state written), as a recomputation needs for
+ * the last level of a segment. Enqueued only, like lbm_step_async: no reductions, no non-finite
+ * report. Results are bitwise those of lbm_step from the same state. For checkpoint
+ * recomputation that keeps every level without copying states. Errors: LBM_ERR_ARG for a NULL
+ * source, for NULL d_dst and d_fields together, or overlapping buffers; LBM_ERR_HIP. */
 lbm_status lbm_step_from(lbm_ctx* ctx, const void* d_src, void* d_dst, void* d_fields);
 
 /* Writes dL/dS_T for L = m^p(T) into d_adj, given the state d_state (lbm_state_bytes, as from

@@ -138,9 +138,7 @@ def adjoint_gradients(sim, steps, checkpoint, cps, final_state, keep_fields=True
                 lam, lam2 = lam2, lam
             continue
         if bufs is None:
-            # bufs[k] holds level s0 + k (k >= 1); bufs[0] takes the output of the segment's last
-            # step, which is only run for its fields
-            bufs = [sim.new_state() for _ in range(checkpoint)]
+            bufs = [None] + [sim.new_state() for _ in range(checkpoint - 1)]  # bufs[k]: level s0 + k
             if keep_fields:
                 fields = [sim.new_fields() for _ in range(checkpoint)]
         seg = [cps[s0]] + bufs[1:s1 - s0]
@@ -149,7 +147,7 @@ def adjoint_gradients(sim, steps, checkpoint, cps, final_state, keep_fields=True
             if t < s1 - 1:
                 sim.step_from(seg[k], seg[k + 1], fields[k] if keep_fields else None)
             elif keep_fields:
-                sim.step_from(seg[k], bufs[0], fields[k])
+                sim.step_from(seg[k], None, fields[k])  # the segment's last level: its fields only
         for t in range(s1 - 1, s0 - 1, -1):
             sim.adjoint_step(seg[t - s0], lam, lam2, scratch, gth, gxi,
                              fields=fields[t - s0] if keep_fields else None)

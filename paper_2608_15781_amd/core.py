@@ -250,15 +250,18 @@ class Lbm:
 
     def step_from(self, src, dst, fields=None):
         """One enqueued step from the state in `src` into `dst` (state buffers, as from get_state or
-        new_state); keeps its level-t fields in `fields` if given. The context's own state and step
-        count do not change."""
+        new_state); keeps its level-t fields in `fields` if given. With dst None only the fields
+        are computed (no collision). The context's own state and step count do not change."""
         self._need(src, self.state_bytes, "source state")
-        self._need(dst, self.state_bytes, "destination state")
+        dp = None
+        if dst is not None:
+            self._need(dst, self.state_bytes, "destination state")
+            dp = dst.data_ptr()
         fp = None
         if fields is not None:
             self._need(fields, self.fields_bytes(), "fields")
             fp = fields.data_ptr()
-        self._check(lib().lbm_step_from(self._h, src.data_ptr(), dst.data_ptr(), fp), self._h)
+        self._check(lib().lbm_step_from(self._h, src.data_ptr(), dp, fp), self._h)
 
     def step_chain(self, states, fields=None):
         """len(states) - 1 enqueued steps, states[k] -> states[k + 1] (lbm_step_from), keeping the

@@ -462,9 +462,10 @@ void use_fields(lbm_ctx* c, StepArgs<P>& A, void* fields) {
   A.rm_out = reinterpret_cast<R*>(fb + FL.rm);
 }
 
-// The four kernels of one step, with optional events (5) around them.
+// The four kernels of one step, with optional events (5) around them; without `collide` only
+// the level-t fields (colour, extrapolation, normals).
 template <int P>
-lbm_status enqueue_step(lbm_ctx* c, const StepArgs<P>& A, hipEvent_t* ev) {
+lbm_status enqueue_step(lbm_ctx* c, const StepArgs<P>& A, hipEvent_t* ev, bool collide = true) {
   const dim3 block(kBlock), gf(c->nb_fluid), ge(c->nb_ext);
   if (ev) HIP_TRY(c, hipEventRecord(ev[0], c->stream));
   if (c->nb_fluid) hipLaunchKernelGGL(k_colour<P>, gf, block, 0, c->stream, A);
@@ -473,7 +474,7 @@ lbm_status enqueue_step(lbm_ctx* c, const StepArgs<P>& A, hipEvent_t* ev) {
   if (ev) HIP_TRY(c, hipEventRecord(ev[2], c->stream));
   if (c->nb_fluid) hipLaunchKernelGGL(k_normal<P>, gf, block, 0, c->stream, A);
   if (ev) HIP_TRY(c, hipEventRecord(ev[3], c->stream));
-  if (c->nb_fluid) hipLaunchKernelGGL((k_collide<P, false>), gf, block, 0, c->stream, A);
+  if (collide && c->nb_fluid) hipLaunchKernelGGL((k_collide<P, false>), gf, block, 0, c->stream, A);
   if (ev) HIP_TRY(c, hipEventRecord(ev[4], c->stream));
   HIP_TRY(c, hipGetLastError());
   return LBM_OK;
@@ -512,15 +513,15 @@ lbm_status launch_step_from(lbm_ctx* c, const void* src, void* dst, void* fields
   A.fin = reinterpret_cast<const S*>(sb + c->L.f_off);
   A.ain = reinterpret_cast<const R*>(sb + c->L.a_off);
   A.gin = reinterpret_cast<const S*>(sb + c->L.g_off);
-  A.fout = reinterpret_cast<S*>(db + c->L.f_off);
-  A.aout = reinterpret_cast<R*>(db + c->L.a_off);
-  A.gout = reinterpret_cast<S*>(db + c->L.g_off);
+  A.fout = db ? reinterpret_cast<S*>(db + c->L.f_off) : nullptr;
+  A.aout = db ? reinterpret_cast<R*>(db + c->L.a_off) : nullptr;
+  A.gout = db ? reinterpret_cast<S*>(db + c->L.g_off) : nullptr;
   if (fields) use_fields<P>(c, A, fields);
   A.ring_row = reinterpret_cast<double*>(c->ws + c->L.ring);
   A.red_in = A.partials;
   A.red_n = c->nb_fluid;
   A.red_out = nullptr;
-  return enqueue_step<P>(c, A, nullptr);
+  return enqueue_step<P>(c, A, nullptr, db != nullptr);  // no destination: the fields only
 }
 
 // Final reduction of the last step of a chunk (ring row `slot`).
@@ -962,12 +963,13 @@ lbm_status lbm_step_fields(lbm_ctx* c, void* d_fields) {
 
 lbm_status lbm_step_from(lbm_ctx* c, const void* d_src, void* d_dst, void* d_fields) {
   if (!c) return LBM_ERR_ARG;
-  if (!d_src || !d_dst) return fail(c, LBM_ERR_ARG, "source and destination states are required");
+  if (!d_src) return fail(c, LBM_ERR_ARG, "a source state is required");
+  if (!d_dst && !d_fields) return fail(c, LBM_ERR_ARG, "a destination state or a fields buffer is required");
   const size_t sb = c->L.state_bytes;
-  if (overlap(d_src, sb, d_dst, sb)) return fail(c, LBM_ERR_ARG, "source and destination states overlap");
+  if (d_dst && overlap(d_src, sb, d_dst, sb)) return fail(c, LBM_ERR_ARG, "source and destination states overlap");
   if (d_fields) {
     const size_t fb = make_field_layout(c->p).total;
-    if (overlap(d_fields, fb, d_dst, sb) || overlap(d_fields, fb, d_src, sb))
+    if ((d_dst && overlap(d_fields, fb, d_dst, sb)) || overlap(d_fields, fb, d_src, sb))
       return fail(c, LBM_ERR_ARG, "the fields buffer overlaps a state");
   }
   DISPATCH(c, launch_step_from, d_src, d_dst, d_fields);

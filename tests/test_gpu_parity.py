@@ -316,7 +316,8 @@ def test_checkpoint_roundtrip_and_determinism(core, oracle_mod):
 @pytest.mark.parametrize("precision", ["fp64", "fp16"])
 def test_step_between_buffers(core, precision):
     """lbm_step_from: steps between caller buffers are bitwise those of lbm_step, keep the same
-    fields as lbm_step_fields and leave the context's own state alone; aliased buffers are refused."""
+    fields as lbm_step_fields (also without a destination, fields only) and leave the context's
+    own state alone; aliased buffers, and neither a destination nor fields, are refused."""
     shape = (19, 13, 11)
     solid, theta, rr0, rp0 = _full_case(shape, seed=29)
     kw = dict(FULL_KW)
@@ -336,6 +337,16 @@ def test_step_between_buffers(core, precision):
     a.step(2)
     assert np.array_equal(fa.cpu().numpy(), fb.cpu().numpy())
     assert np.array_equal(a.get_state().cpu().numpy(), bufs[2].cpu().numpy())
+    # no destination: the same level-9 fields, and no state written
+    fc = a.new_fields().zero_()
+    s0_before = s0.clone()
+    a.step_from(s0, None, fc)
+    assert np.array_equal(fc.cpu().numpy(), fa.cpu().numpy())
+    assert np.array_equal(s0.cpu().numpy(), s0_before.cpu().numpy())
+    assert np.array_equal(a.get_state().cpu().numpy(), bufs[2].cpu().numpy())
+    with pytest.raises(core.LbmError) as e:
+        a.step_from(s0, None, None)
+    assert e.value.status == core.LBM_ERR_ARG
     with pytest.raises(core.LbmError) as e:
         a.step_from(bufs[0], bufs[0])
     assert e.value.status == core.LBM_ERR_ARG
