@@ -1,17 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of the reactive colour-gradient lattice Boltzmann step on one MI355X.
 
-Workload: 128^3 porous mask (thresholded Gaussian random field, 512 plane waves of wavelength 16,
-seed 2, ~50% porosity), two colours on D3Q19 with the central-moment collision, surface tension
-0.01, Akai wetting at 60 degrees, body force 1e-6 along x on both colours, wall reaction xi = 1e-3,
-D3Q7 species with inlet C = 1 at x = 0, all-reactant start. FP32 populations (the headline), and
-FP16 / BF16 deviation storage with FP32 arithmetic; errors of each after the timed steps against
-an FP64 run of the same library. One step = one pass of the whole step over the lattice; the
-state is resident in HBM before the timed region starts.
+Headline workload: 512^3 porous mask (thresholded Gaussian random field, 512 plane waves of
+wavelength 32, seed 5, porosity 0.55), two colours on D3Q19 with the central-moment collision,
+surface tension 0.01, Akai wetting at 30 degrees, body force 1e-6 along x on both colours, wall
+reaction xi = 1e-3, D3Q7 species with inlet C = 1 at x = 0, all-reactant start. FP32 populations
+(the headline value) and FP16 deviation storage with FP32 arithmetic beside it (its fields and
+conversion compared with the FP32 run). One step = one pass of the whole step over the lattice;
+the state is resident in HBM before the timed region starts.
 
-Adjoint: 96^3 mask (wavelength 12, seed 4), contact angles 90 +- 10 degrees per node, 200 FP32
-steps with a checkpoint every 20; the backward pass (recompute + adjoint steps) of the gas
-production L = m^p(200) - m^p(0) is timed, and its gradients are compared with the FP64 ones.
+Roofline: the whole step against HBM, with the algorithmic bytes per fluid update of the
+45-population representation (each population read once and written once, plus a flag byte:
+2 x 45 x 4 + 1 = 361 B in FP32, 181 B with 2-byte storage), divided by the step's device time
+measured with HIP events on the library's stream.
+
+Beside the headline: the 128^3 workload (wavelength 16, seed 2, 60 degrees) in FP32, FP16 and BF16
+storage with errors against an FP64 run of the same library; the adjoint on the 96^3 workload
+(wavelength 12, seed 4), contact angles 90 +- 10 degrees per node, 200 FP32 steps with a checkpoint
+every 20: the backward pass (recompute + adjoint steps) of the gas production
+L = m^p(200) - m^p(0) is timed and its gradients compared with the FP64 ones; and the FP64 CPU
+oracle on a 128^3 crop of the headline mask.
 
 Prints one JSON line. value = million fluid-node updates per second (MFLUPS).
 """
@@ -21,58 +29,49 @@ import os
 import sys
 import time
 
-import numpy as np
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS and % HBM roofline, FP32 vs FP16-storage vs adjoint, at stated error"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-WORKLOAD = "bijel128"
+HEADLINE = "bijel512"  # the largest single-GPU workload
+SIDE = "bijel128"      # error modes against FP64
 
 
 def bytes_per_fluid_update(precision):
-    """Algorithmic bytes per fluid node of each kernel (each array element moved once).
+    """Algorithmic bytes per fluid update.
 
-    State per node: 19 colour-blind populations and 7 species populations in storage precision
-    (s bytes), 4 colour scalars (a, v) in arithmetic precision (r bytes); info word 4 bytes.
+    naive45: the 45-population representation (38 colour + 7 species), each population read once
+    and written once in storage precision s, plus a flag byte. step_min: the compact state this
+    library stores (19 colour-blind + 7 species populations in s bytes, 4 colour scalars in
+    arithmetic precision r), read once and written once, plus the 4-byte info word.
     """
     s = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[precision]
     r = 8 if precision == "fp64" else 4
-    colour = 19 * s + 4 * r + 4 + r                  # pull f^m, (a, v); info; write rho^N
-    normal = r + 4 + 4 * r + 4 * r                   # rho^N; info; wetting data; write n*, |G|
-    collide = 26 * s + r + 4 * r + 4 + 26 * s + 4 * r  # pull f^m, g; rho^N; n*, |G|; info; write state
-    step_min = 2 * (26 * s + 4 * r) + 4              # state read once and written once, info
-    naive = 2 * 45 * s + 1                           # 45 per-colour populations in and out, flag byte
-    return dict(colour=colour, normal=normal, collide=collide, step_min=step_min, naive45=naive)
+    return dict(naive45=2 * 45 * s + 1, step_min=2 * (26 * s + 4 * r) + 4)
 
 
-def measured_traffic(precision, kernel):
-    """Calibrated HBM bytes per launch of a kernel from the committed counter summary, or None.
-
-    The summary records the hash of the HIP sources it was taken on; a different hash means the
-    kernels changed since, and the figure no longer applies.
-    """
-    path = os.path.join(ROOT, "profiles", "step_kernels_bijel128_%s.md" % precision)
+def measured_step_traffic(workload, precision, kernels):
+    """Calibrated HBM bytes of one step (sum over its kernels) from the committed counter summary
+    of that workload, or None. The summary records the hash of the HIP sources it was taken on;
+    a different hash means the kernels changed since, and the figure no longer applies."""
+    path = os.path.join(ROOT, "profiles", "step_kernels_%s_%s.md" % (workload, precision))
     if not os.path.exists(path):
         return None
     from paper_2608_15781_amd import build as lbm_build
 
-    digest, val = None, None
+    digest, vals = None, {}
     with open(path) as f:
         for line in f:
             if line.startswith("- source_digest: "):
                 digest = line.split(": ", 1)[1].strip()
-            elif line.startswith("- traffic_bytes_per_launch %s: " % kernel):
-                val = float(line.rsplit(": ", 1)[1])
-    return val if digest == lbm_build.source_digest() else None
-
-
-def make_inputs(device):
-    from paper_2608_15781_amd import inputs
-
-    w, solid, theta, rr0, rp0 = inputs.workload_inputs(WORKLOAD, device=device)
-    return w, solid, theta, rr0, rp0
+            elif line.startswith("- traffic_bytes_per_launch "):
+                name, val = line[len("- traffic_bytes_per_launch "):].rsplit(": ", 1)
+                vals[name] = float(val)
+    if digest != lbm_build.source_digest():
+        return None
+    picked = [v for k, v in vals.items() if any(k.startswith(kn) for kn in kernels)]
+    return sum(picked) if picked else None
 
 
 def sim_kwargs(w):
@@ -80,7 +79,9 @@ def sim_kwargs(w):
                 species=w["species"], x_open=w["x_open"], tau_species=w["tau_c"], c_inlet=w["c_in"])
 
 
-def run_mode(core, torch, w, solid, theta, rr0, rp0, precision, steps, warmup, profile):
+def run_mode(core, torch, w, solid, theta, rr0, rp0, precision, steps, warmup, profile, fields=True):
+    """W untimed steps, then K steps timed with the host clock between device synchronisations;
+    then (profile) K more steps with HIP events around every kernel on the library's stream."""
     sim = core.Lbm(w["shape"], solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision=precision,
                    **sim_kwargs(w))
     sim.step(warmup, reductions=False)
@@ -89,13 +90,13 @@ def run_mode(core, torch, w, solid, theta, rr0, rp0, precision, steps, warmup, p
     red = sim.step(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    mom = {k: v.clone() for k, v in sim.moments().items()}  # fields after warmup + steps
+    mom = {k: v.clone() for k, v in sim.moments().items()} if fields else None  # after warmup + steps
     kern = None
     if profile:
         sim.set_profiling(True)
         sim.step(steps, reductions=False)
         ms, n = sim.kernel_times()
-        kern = {k: v / n for k, v in ms.items()}
+        kern = {k: v / n for k, v in ms.items() if v > 0}
         sim.set_profiling(False)
     return sim, red, dt, kern, mom
 
@@ -181,29 +182,58 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(w, solid, theta, rr0, rp0, nfluid, steps):
+def cpu_baseline(w, solid, theta, rr0, rp0, steps, size=128):
+    """The FP64 oracle on the leading size^3 corner of the headline mask (same wavelength,
+    threshold, angle and physics), timed on all host cores."""
     import oracle
+    from paper_2608_15781_amd import inputs
 
+    c = [inputs.crop(a, size) for a in (solid, theta, rr0, rp0)]
+    nfluid = int((c[0] == 0).sum())
     kw = dict(tau=w["tau"], sigma=w["sigma"], beta=w["beta"], accel=[(w["accel"], 0, 0)] * 2,
               species=w["species"], x_open=w["x_open"], tau_c=w["tau_c"], c_in=w["c_in"])
-    o = oracle.Oracle(w["shape"], solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, xi=w["xi"], **kw)
+    o = oracle.Oracle((size, size, size), solid=c[0], theta=c[1], rho_r0=c[2], rho_p0=c[3], xi=w["xi"], **kw)
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
     return dict(value=nfluid * steps / dt / 1e6, unit="MFLUPS", cores=oracle.get_threads(), kind="oracle",
-                sample="%d steps of the full 128^3 workload (FP64, OpenMP over z), %.1f s" % (steps, dt),
+                sample="%d steps of the leading %d^3 corner of the 512^3 mask (%d fluid nodes; FP64, OpenMP "
+                       "over z), %.1f s" % (steps, size, nfluid, dt),
                 cpu_model=cpu_model())
+
+
+def step_roofline(mflups, kern, nfluid, precision, workload, copy_gbs):
+    """The whole step against HBM: algorithmic bytes of the 45-population representation per
+    fluid update, over the step's device time (sum of its kernels' HIP-event averages)."""
+    b = bytes_per_fluid_update(precision)
+    step_s = sum(kern.values()) * 1e-3
+    achieved = b["naive45"] * nfluid / step_s / 1e9
+    traffic = measured_step_traffic(workload, precision, ["lbm::k_"])
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "kernel": "one step (%s)" % " + ".join("k_" + k for k in kern),
+           "alg_bytes_per_fluid_update": b["naive45"], "fluid_nodes_per_launch": nfluid,
+           "avg_step_ms": round(step_s * 1e3, 5),
+           "frac_from_mflups": round(mflups * 1e6 * b["naive45"] / (HBM_PEAK_GBS * 1e9), 4),
+           "compact_state_bytes_per_fluid_update": b["step_min"],
+           "compact_state_frac": round(b["step_min"] * nfluid / step_s / 1e9 / HBM_PEAK_GBS, 4),
+           "device_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+           "kernel_ms": {k: round(v, 5) for k, v in kern.items()}}
+    if traffic is not None:
+        out["traffic_bytes_per_fluid_update"] = round(traffic / nfluid, 1)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--side-steps", type=int, default=2000, help="steps of the 128^3 error modes")
+    ap.add_argument("--cpu-steps", type=int, default=48)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-side", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--modes", default="fp16,bf16", help="extra storage precisions to time")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path (the step would shard by "
@@ -213,50 +243,67 @@ def main():
 
     import torch
 
-    from paper_2608_15781_amd import core
+    from paper_2608_15781_amd import core, inputs
 
     core.lib()
-    print("bench: building %s inputs" % WORKLOAD, file=sys.stderr, flush=True)
-    w, solid, theta, rr0, rp0 = make_inputs("cuda:0")
+    print("bench: building %s inputs" % HEADLINE, file=sys.stderr, flush=True)
+    w, solid, theta, rr0, rp0 = inputs.workload_inputs(HEADLINE, device="cuda:0")
     nfluid = int((solid == 0).sum())
     nx, ny, nz = w["shape"]
     nall = nx * ny * nz
+    # the achievable streaming rate, measured first: it also brings the GPU out of idle before
+    # the timed region
+    copy_gbs = device_copy_gbs(torch)
 
     print("bench: fp32 headline, %d warmup + %d timed steps" % (args.warmup, args.steps), file=sys.stderr, flush=True)
-    sim32, red32, dt32, kern32, mom32 = run_mode(core, torch, w, solid, theta, rr0, rp0, "fp32", args.steps, args.warmup,
-                                          profile=True)
+    sim32, red32, dt32, kern32, mom32 = run_mode(core, torch, w, solid, theta, rr0, rp0, "fp32", args.steps,
+                                                 args.warmup, profile=True)
     mflups = nfluid * args.steps / dt32 / 1e6
     ms_step = dt32 * 1e3 / args.steps
-    b = bytes_per_fluid_update("fp32")
-    coll_s = kern32["collide"] * 1e-3
-    achieved = b["collide"] * nfluid / coll_s / 1e9
-
-    # Reference: the same steps in FP64 storage and arithmetic.
-    print("bench: fp64 reference run", file=sys.stderr, flush=True)
-    sim64, red64, dt64, _, m64 = run_mode(core, torch, w, solid, theta, rr0, rp0, "fp64", args.steps, args.warmup,
-                                     profile=False)
-    conv64 = red64[:, 2].sum()
-
-    def errors(m, red):
-        rm = m["rho_r"] + m["rho_p"]
-        rm64 = m64["rho_r"] + m64["rho_p"]
-        return dict(rho_m=rel_l2(rm, rm64), u=rel_l2(m["u"], m64["u"]), rho_n=rel_l2(m["rho_n"], m64["rho_n"]),
-                    c=rel_l2(m["c"], m64["c"]), conversion=float(abs(red[:, 2].sum() - conv64) / conv64))
-
-    err32 = errors(mom32, red32)
-    modes = {"fp32": dict(mflups=mflups, ms_per_step=ms_step, error_vs_fp64=err32, kernel_ms=kern32),
-             "fp64": dict(mflups=nfluid * args.steps / dt64 / 1e6, ms_per_step=dt64 * 1e3 / args.steps)}
     del sim32
-    for prec in [m for m in args.modes.split(",") if m]:
-        print("bench: %s mode" % prec, file=sys.stderr, flush=True)
-        sim, red, dt, kern, mom = run_mode(core, torch, w, solid, theta, rr0, rp0, prec, args.steps, args.warmup,
-                                           profile=True)
-        bp = bytes_per_fluid_update(prec)
-        modes[prec] = dict(mflups=nfluid * args.steps / dt / 1e6, ms_per_step=dt * 1e3 / args.steps,
-                           error_vs_fp64=errors(mom, red), kernel_ms=kern,
-                           collide_gbs=bp["collide"] * nfluid / (kern["collide"] * 1e-3) / 1e9)
-        del sim
-    del sim64
+    print("bench: fp16 storage, %d warmup + %d timed steps" % (args.warmup, args.steps), file=sys.stderr, flush=True)
+    sim16, red16, dt16, kern16, mom16 = run_mode(core, torch, w, solid, theta, rr0, rp0, "fp16", args.steps,
+                                                 args.warmup, profile=True)
+    del sim16
+    mfl16 = nfluid * args.steps / dt16 / 1e6
+    conv32, conv16 = float(red32[:, 2].sum()), float(red16[:, 2].sum())
+    fp16 = dict(mflups=round(mfl16, 1), ms_per_step=round(dt16 * 1e3 / args.steps, 5),
+                roofline=step_roofline(mfl16, kern16, nfluid, "fp16", HEADLINE, copy_gbs),
+                vs_fp32=dict(steps=args.warmup + args.steps,
+                             rho_m=rel_l2(mom16["rho_r"] + mom16["rho_p"], mom32["rho_r"] + mom32["rho_p"]),
+                             u=rel_l2(mom16["u"], mom32["u"]), rho_n=rel_l2(mom16["rho_n"], mom32["rho_n"]),
+                             c=rel_l2(mom16["c"], mom32["c"]),
+                             conversion_efficiency=conv16 / conv32 if conv32 else None))
+    del mom16, mom32
+    torch.cuda.empty_cache()
+
+    side = None
+    if not args.no_side:
+        print("bench: %s modes (fp64 reference, fp32, fp16, bf16), %d steps" % (SIDE, args.side_steps),
+              file=sys.stderr, flush=True)
+        ws, ss, ths, rrs, rps = inputs.workload_inputs(SIDE, device="cuda:0")
+        nfs = int((ss == 0).sum())
+        _, red64, dt64, _, m64 = run_mode(core, torch, ws, ss, ths, rrs, rps, "fp64", args.side_steps, 100,
+                                          profile=False)
+        conv64 = red64[:, 2].sum()
+        side = dict(workload="128^3 porous GRF mask (wavelength 16, seed 2, porosity %.3f), theta 60 deg, "
+                             "errors after %d steps against the library's FP64 run" % (nfs / ss.size,
+                                                                                        100 + args.side_steps),
+                    fluid_nodes=nfs,
+                    modes={"fp64": dict(mflups=round(nfs * args.side_steps / dt64 / 1e6, 1))})
+        for prec in ("fp32", "fp16", "bf16"):
+            sim, red, dt, kern, m = run_mode(core, torch, ws, ss, ths, rrs, rps, prec, args.side_steps, 100,
+                                             profile=True)
+            del sim
+            mfl = nfs * args.side_steps / dt / 1e6
+            side["modes"][prec] = dict(
+                mflups=round(mfl, 1), roofline=step_roofline(mfl, kern, nfs, prec, SIDE, copy_gbs),
+                error_vs_fp64=dict(rho_m=rel_l2(m["rho_r"] + m["rho_p"], m64["rho_r"] + m64["rho_p"]),
+                                   u=rel_l2(m["u"], m64["u"]), rho_n=rel_l2(m["rho_n"], m64["rho_n"]),
+                                   c=rel_l2(m["c"], m64["c"]),
+                                   conversion=float(abs(red[:, 2].sum() - conv64) / conv64)))
+        del m64
+        torch.cuda.empty_cache()
 
     adjoint = None
     if not args.no_adjoint:
@@ -288,11 +335,8 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        print("bench: cpu baseline (oracle, %d steps)" % args.cpu_steps, file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w, solid, theta, rr0, rp0, nfluid, args.cpu_steps)
-
-    traffic = measured_traffic("fp32", "lbm::k_collide<1, false>")
-    copy_gbs = device_copy_gbs(torch)
+        print("bench: cpu baseline (oracle, %d steps on a 128^3 corner)" % args.cpu_steps, file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, solid, theta, rr0, rp0, args.cpu_steps)
 
     out = {
         "metric": METRIC,
@@ -307,19 +351,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "128^3 porous GRF mask (wavelength 16, seed 2, porosity %.3f), D3Q19 two-colour "
-                               "CG-LBM + D3Q7 species, FP32 storage" % (nfluid / nall),
+        "config": {"workload": "512^3 porous GRF mask (wavelength 32, seed 5, porosity %.3f), contact angle 30 deg, "
+                               "D3Q19 two-colour CG-LBM + D3Q7 species, FP32 storage" % (nfluid / nall),
                    "lattice": [nx, ny, nz], "fluid_nodes": nfluid, "parallelism": "single GPU"},
         "mlups_all_nodes": round(nall * args.steps / dt32 / 1e6, 1),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_collide",
-                     "alg_bytes_per_fluid_node": b["collide"], "avg_launch_ms": round(kern32["collide"], 5),
-                     "device_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
-        "step_roofline": {"alg_bytes_per_fluid_update": b["step_min"],
-                          "frac": round(mflups * 1e6 * b["step_min"] / (HBM_PEAK_GBS * 1e9), 4),
-                          "naive45_bytes_per_fluid_update": b["naive45"],
-                          "naive45_equiv_frac": round(mflups * 1e6 * b["naive45"] / (HBM_PEAK_GBS * 1e9), 4)},
-        "modes": modes,
+        "roofline": step_roofline(mflups, kern32, nfluid, "fp32", HEADLINE, copy_gbs),
+        "fp16_storage": fp16,
+        "side_128": side,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
     }

@@ -213,6 +213,17 @@ lbm_status lbm_step_fields(lbm_ctx* ctx, void* d_fields);
  * source, for NULL d_dst and d_fields together, or overlapping buffers; LBM_ERR_HIP. */
 lbm_status lbm_step_from(lbm_ctx* ctx, const void* d_src, void* d_dst, void* d_fields);
 
+/* FP64 sums of the stored state d_state (lbm_state_bytes, as from lbm_get_state; NULL = the
+ * context's current state), computed on the device: mass_r and mass_p are the colour masses of
+ * its level (eqs. reactant_mass, product_mass: every stored population is pulled exactly once,
+ * so the sum over the stored state equals the sum over the pulled level), species_total the
+ * stored species total, nonfinite the count of fluid nodes holding a non-finite value;
+ * conversion is 0 (it belongs to a step, not to a state). mass_p is the quantity whose
+ * derivative lbm_adjoint_seed writes, so L = m^p(T) - m^p(0) of the adjoint is the difference
+ * of two such calls. Uses the context's per-step partial sums (free between calls) and
+ * synchronizes the stream. Errors: LBM_ERR_ARG for a NULL out, LBM_ERR_HIP. */
+lbm_status lbm_state_sums(lbm_ctx* ctx, const void* d_state, lbm_reductions* out);
+
 /* Writes dL/dS_T for L = m^p(T) into d_adj, given the state d_state (lbm_state_bytes, as from
  * lbm_get_state) of level T. Stream-ordered. */
 lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const void* d_state, void* d_adj);
@@ -245,7 +256,8 @@ int64_t lbm_steps_done(const lbm_ctx* ctx);
 /* Releases the context (host memory only; the workspace belongs to the caller). */
 void lbm_free(lbm_ctx* ctx);
 
-/* Message of the last error on this context (static or context-owned storage; never NULL). */
+/* Message of the last error on this context (context-owned storage), or with ctx NULL of the
+ * last failed call without a context on the calling thread (thread-local storage); never NULL. */
 const char* lbm_last_error(const lbm_ctx* ctx);
 
 #ifdef __cplusplus

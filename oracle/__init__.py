@@ -70,6 +70,8 @@ def lib():
         _lib.orc_feq.argtypes = [d, vp, vp]
         _lib.orc_cm_back.argtypes = [vp, vp, vp]
         _lib.orc_wetting.argtypes = [vp, vp, d, vp, vp, vp]
+        _lib.orc_set_akai_cone.argtypes = [d]
+        _lib.orc_set_akai_cone.restype = d
         _lib.orc_set_threads.argtypes = [i32]
         _lib.orc_get_threads.restype = i32
         _lib.orc_max_dirs.restype = i32
@@ -205,6 +207,12 @@ def wetting(n, ns, theta):
     out, np_, nm = np.zeros(3), np.zeros(3), np.zeros(3)
     lib().orc_wetting(_ptr(_f64(n)), _ptr(_f64(ns)), float(theta), _ptr(out), _ptr(np_), _ptr(nm))
     return out, np_, nm
+
+
+def set_akai_cone(s: float) -> float:
+    """Sets the sine of the half-angle of the cone around +-n_s inside which the Akai
+    realignment keeps n (1e-2 by default, as in the library); returns the previous value."""
+    return float(lib().orc_set_akai_cone(float(s)))
 
 
 def set_threads(n: int):

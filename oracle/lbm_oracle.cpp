@@ -228,7 +228,9 @@ void cm_back_transform(const T& ux, const T& uy, const T& uz, const T k[5], T d[
 // too small to define a plane, and rotating on it would feed rounding noise into the colour field
 // (the realigned normal drives recolouring along itself, so any gain above one near the axis grows
 // the noise from step to step). The bound also caps the 1/sin(theta') amplification at 100.
-constexpr double kAkaiCone = 1e-2;
+// The tests can narrow or widen the cone (orc_set_akai_cone) to show that the equilibrium angle
+// does not depend on it.
+double kAkaiCone = 1e-2;
 
 template <class T>
 void wetting_realign(const T n[3], const double ns[3], const T& theta, T out[3], T np[3], T nm[3]) {
@@ -673,6 +675,14 @@ void orc_feq(double rho, const double* u, double* out) {
 
 void orc_cm_back(const double* u, const double* k5_9, double* out) {
   cm_back_transform(u[0], u[1], u[2], k5_9, out);
+}
+
+// Half-width of the cone around +-n_s in which n is kept (sin(theta') below it); returns the previous
+// value. Test knob: the library's cone is fixed at 1e-2.
+double orc_set_akai_cone(double s) {
+  const double old = kAkaiCone;
+  kAkaiCone = s;
+  return old;
 }
 
 void orc_wetting(const double* n, const double* ns, double theta, double* nstar, double* np, double* nm) {

@@ -7,7 +7,8 @@ the library (lbm_adjoint_seed / lbm_adjoint_step) with checkpoint-and-recompute 
 forward pass keeps the state every ``problem["checkpoint"]`` steps, and the last segment whole;
 the backward pass runs the adjoint steps backwards through that segment, then restores each
 earlier checkpoint in reverse order, recomputes that segment's states, and runs the adjoint steps
-backwards through it. Memory: one state per checkpoint plus one segment of states and fields.
+backwards through it. Memory: one state per checkpoint plus one segment of states and fields
+(the kept last segment's buffers are reused for the recomputation once its sweep is done).
 ``problem["checkpoint"] = 0`` keeps every level instead (state and forward fields, written
 straight into buffers of their own by the forward pass), and the backward pass recomputes
 nothing: faster, for T levels of memory.
@@ -67,7 +68,9 @@ def forward_states(sim, steps, checkpoint):
 
 
 def _product_mass(sim):
-    return float(sim.moments()["rho_p"].double().sum())
+    """m^p of the current level, summed in FP64 on the device by the library (lbm_state_sums): the
+    quantity whose derivative the adjoint seed writes."""
+    return sim.state_sums()["mass_p"]
 
 
 def forward_keep_all(sim, steps):
@@ -98,8 +101,7 @@ def adjoint_gradients_keep_all(sim, levels, final_state):
     lam = sim.new_adjoint()
     lam2 = sim.new_adjoint()
     scratch = sim.new_scratch()
-    gth = torch.zeros(sim.N, dtype=torch.float64, device=dev)
-    gxi = torch.zeros(1, dtype=torch.float64, device=dev)
+    gth, gxi = sim.new_gradients()
     sim.adjoint_seed(final_state, lam)
     for t in range(len(states) - 1, -1, -1):
         sim.adjoint_step(states[t], lam, lam2, scratch, gth, gxi, fields=fields[t])
@@ -116,31 +118,43 @@ def adjoint_gradients(sim, steps, checkpoint, cps, final_state, keep_fields=True
     into a buffer of its own, so no state is copied. With keep_fields the recomputation also keeps
     every level's rho^N, n* and rho^m, which the adjoint steps then reuse instead of recomputing
     (same values bit for bit). The last segment, when the forward pass kept it (forward_states),
-    is not recomputed. Memory: `checkpoint` state buffers, plus as many field buffers."""
+    is not recomputed; its sweep consumes it (cps.last is cleared) and its buffers then serve the
+    recomputation, so a second sweep over the same checkpoints recomputes that segment from its
+    checkpoint instead (same gradient bit for bit). Memory: one segment of `checkpoint` state
+    buffers and as many field buffers."""
     dev = sim.device
     lam = sim.new_adjoint()
     lam2 = sim.new_adjoint()
     scratch = sim.new_scratch()
-    gth = torch.zeros(sim.N, dtype=torch.float64, device=dev)
-    gxi = torch.zeros(1, dtype=torch.float64, device=dev)
+    gth, gxi = sim.new_gradients()
     kept = getattr(cps, "last", None)
     bufs = fields = None
+    spare_states, spare_fields = [], []
     sim.adjoint_seed(final_state, lam)
     starts = sorted(cps)
     for s0 in reversed(starts):
         s1 = min(s0 + checkpoint, steps)
         if kept is not None and s0 == kept[0]:
-            # kept whole by the forward pass: no recomputation (and the caller's buffers stay as
-            # they are, so the sweep can be run again)
+            # kept whole by the forward pass: no recomputation
             seg, segf = kept[1], kept[2]
             for t in range(s1 - 1, s0 - 1, -1):
                 sim.adjoint_step(seg[t - s0], lam, lam2, scratch, gth, gxi, fields=segf[t - s0])
                 lam, lam2 = lam2, lam
+            # seg[0] is the checkpoint itself and stays; the other buffers are free now
+            spare_states, spare_fields = list(seg[1:]), list(segf)
+            cps.last = kept = None
             continue
         if bufs is None:
-            bufs = [None] + [sim.new_state() for _ in range(checkpoint - 1)]  # bufs[k]: level s0 + k
+            def state_buf():
+                return spare_states.pop() if spare_states else sim.new_state()
+
+            def fields_buf():
+                return spare_fields.pop() if spare_fields else sim.new_fields()
+
+            bufs = [None] + [state_buf() for _ in range(checkpoint - 1)]  # bufs[k]: level s0 + k
             if keep_fields:
-                fields = [sim.new_fields() for _ in range(checkpoint)]
+                fields = [fields_buf() for _ in range(checkpoint)]
+            spare_states = spare_fields = None
         seg = [cps[s0]] + bufs[1:s1 - s0]
         for t in range(s0, s1):
             k = t - s0

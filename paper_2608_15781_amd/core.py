@@ -21,7 +21,7 @@ EXPORTED = ["lbm_version", "lbm_workspace_bytes", "lbm_state_bytes", "lbm_init",
             "lbm_populations", "lbm_geometry", "lbm_state_layout", "lbm_get_state", "lbm_set_state",
             "lbm_set_profiling", "lbm_kernel_times", "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step",
             "lbm_steps_done", "lbm_free", "lbm_last_error", "lbm_fields_bytes", "lbm_step_fields",
-            "lbm_adjoint_step_fields", "lbm_step_from"]
+            "lbm_adjoint_step_fields", "lbm_step_from", "lbm_state_sums"]
 KERNELS = ("colour", "extrap", "normal", "collide")
 
 
@@ -72,6 +72,7 @@ def lib():
         L.lbm_adjoint_step_fields.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lbm_populations.argtypes = [vp, vp, vp, vp]
+        L.lbm_state_sums.argtypes = [vp, vp, vp]
         L.lbm_geometry.argtypes = [vp, vp, vp]
         L.lbm_get_state.argtypes = [vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, i64]
@@ -216,8 +217,9 @@ class Lbm:
         """Level-t fields as device tensors of shape (nz, ny, nx) ((3, nz, ny, nx) for u)."""
         t = self.torch
         N = self.N
-        rr, rp, rn, c = (t.empty(N, dtype=self.real, device=self.device) for _ in range(4))
-        u = t.empty(3 * N, dtype=self.real, device=self.device)
+        with t.cuda.stream(self.stream):
+            rr, rp, rn, c = (t.empty(N, dtype=self.real, device=self.device) for _ in range(4))
+            u = t.empty(3 * N, dtype=self.real, device=self.device)
         self._check(lib().lbm_moments(self._h, rr.data_ptr(), rp.data_ptr(), rn.data_ptr(), u.data_ptr(),
                                       c.data_ptr()), self._h)
         self.stream.synchronize()
@@ -228,17 +230,19 @@ class Lbm:
         """Post-collision populations per colour, (19, N), (19, N), (7, N) device tensors."""
         t = self.torch
         N = self.N
-        fr = t.empty(19 * N, dtype=self.real, device=self.device)
-        fp = t.empty(19 * N, dtype=self.real, device=self.device)
-        g = t.empty(7 * N, dtype=self.real, device=self.device)
+        with t.cuda.stream(self.stream):
+            fr = t.empty(19 * N, dtype=self.real, device=self.device)
+            fp = t.empty(19 * N, dtype=self.real, device=self.device)
+            g = t.empty(7 * N, dtype=self.real, device=self.device)
         self._check(lib().lbm_populations(self._h, fr.data_ptr(), fp.data_ptr(), g.data_ptr()), self._h)
         self.stream.synchronize()
         return fr.view(19, N), fp.view(19, N), g.view(7, N)
 
     def geometry(self):
         t = self.torch
-        info = t.empty(self.N, dtype=t.int32, device=self.device)
-        wet = t.empty(4 * self.N, dtype=self.real, device=self.device)
+        with t.cuda.stream(self.stream):
+            info = t.empty(self.N, dtype=t.int32, device=self.device)
+            wet = t.empty(4 * self.N, dtype=self.real, device=self.device)
         self._check(lib().lbm_geometry(self._h, info.data_ptr(), wet.data_ptr()), self._h)
         self.stream.synchronize()
         return info, wet.view(self.N, 4).t()
@@ -295,6 +299,19 @@ class Lbm:
             self.stream.synchronize()
         return buf
 
+    def state_sums(self, state=None):
+        """FP64 sums of a stored state, computed by the library on the device (lbm_state_sums):
+        dict with mass_r, mass_p (the colour masses of the state's level), species_total and
+        nonfinite. `state`: a state buffer (as from get_state), or None for the current state."""
+        out = Reductions()
+        ptr = None
+        if state is not None:
+            self._need(state, self.state_bytes, "state")
+            ptr = state.data_ptr()
+        self._check(lib().lbm_state_sums(self._h, ptr, ctypes.byref(out)), self._h)
+        return dict(mass_r=out.mass_r, mass_p=out.mass_p, species_total=out.species_total,
+                    nonfinite=out.nonfinite)
+
     # ---- state layout and adjoint -------------------------------------------------------------
     def state_layout(self):
         """Byte offsets of the population, colour-scalar and species parts of a state snapshot, and
@@ -330,11 +347,20 @@ class Lbm:
 
     def new_adjoint(self):
         """A zeroed adjoint state: (30, P) tensor of the context's real type, P the plane stride;
-        column f < nfluid is the fluid node of rank f."""
-        return self.torch.zeros(30, self.state_layout()[3], dtype=self.real, device=self.device)
+        column f < nfluid is the fluid node of rank f. Allocated and zeroed on the context's
+        stream, so the library's later work on that stream is ordered after the fill."""
+        with self.torch.cuda.stream(self.stream):
+            return self.torch.zeros(30, self.state_layout()[3], dtype=self.real, device=self.device)
 
     def new_scratch(self):
-        return self.torch.empty(self.adjoint_bytes()[1] + 256, dtype=self.torch.uint8, device=self.device)
+        with self.torch.cuda.stream(self.stream):
+            return self.torch.empty(self.adjoint_bytes()[1] + 256, dtype=self.torch.uint8, device=self.device)
+
+    def new_gradients(self):
+        """Zeroed FP64 accumulators (dL/dtheta per node, dL/dxi) on the context's stream."""
+        with self.torch.cuda.stream(self.stream):
+            return (self.torch.zeros(self.N, dtype=self.torch.float64, device=self.device),
+                    self.torch.zeros(1, dtype=self.torch.float64, device=self.device))
 
     @staticmethod
     def _aligned(t):
@@ -367,8 +393,9 @@ class Lbm:
         return self._fields_bytes
 
     def new_fields(self):
-        """A buffer for the forward fields of one level (lbm_step_fields)."""
-        return self.torch.empty(self.fields_bytes(), dtype=self.torch.uint8, device=self.device)
+        """A buffer for the forward fields of one level (lbm_step_fields), on the context's stream."""
+        with self.torch.cuda.stream(self.stream):
+            return self.torch.empty(self.fields_bytes(), dtype=self.torch.uint8, device=self.device)
 
     def step_fields(self, fields):
         """One enqueued step that keeps its level-t fields in `fields` (from new_fields)."""

@@ -189,7 +189,8 @@ lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail((ctx), LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-char g_err[512] = "";
+// Message of the last error of a call without a context (lbm_last_error(NULL)), per thread.
+thread_local char g_err[512] = "";
 
 lbm_status check_params(const lbm_params* p, char* msg, size_t len) {
   if (!p) { snprintf(msg, len, "params is NULL"); return LBM_ERR_ARG; }
@@ -670,6 +671,21 @@ StepArgs<P> make_args_from(lbm_ctx* c, const void* state) {
   return A;
 }
 
+// FP64 sums of a stored state into `out` (host, 5 doubles). The per-step partials and the first
+// reduction-ring row are free between calls, so they serve here.
+template <int P>
+lbm_status launch_state_sums(lbm_ctx* c, const void* state, double* out) {
+  StepArgs<P> A = state ? make_args_from<P>(c, state) : make_args<P>(c, c->cur);
+  double* row = reinterpret_cast<double*>(c->ws + c->L.ring);
+  if (c->nb_fluid)
+    hipLaunchKernelGGL(k_state_sums<P>, dim3(c->nb_fluid), dim3(kBlock), 0, c->stream, A);
+  hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlock), 0, c->stream, A.partials, c->nb_fluid, row);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipMemcpyAsync(out, row, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
 template <int P>
 lbm_status launch_adj_seed(lbm_ctx* c, const void* state, void* adj) {
   using R = typename Prec<P>::R;
@@ -684,10 +700,10 @@ lbm_status launch_adj_seed(lbm_ctx* c, const void* state, void* adj) {
 
 template <int P>
 lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* fields, const void* lin, void* lout,
-                           void* scratch, double* gth, double* gxi) {
+                           void* scr, double* gth, double* gxi) {
   using R = typename Prec<P>::R;
   const AdjLayout AL = make_adj_layout(c->p);
-  char* sc = static_cast<char*>(scratch);
+  char* sc = static_cast<char*>(scr);
   StepArgs<P> A = make_args_from<P>(c, state);
   A.rm_out = reinterpret_cast<R*>(sc + AL.rmv);
   A.nraw = reinterpret_cast<R*>(sc + AL.nraw);
@@ -730,16 +746,16 @@ lbm_status launch_adj_step(lbm_ctx* c, const void* state, const void* fields, co
 // The buffers one adjoint step writes (adjoint output, scratch) must not overlap anything it
 // reads or writes (state, fields, adjoint input, each other).
 lbm_status check_adjoint_buffers(lbm_ctx* c, const void* state, const void* fields, const void* lin,
-                                 const void* lout, const void* scratch) {
+                                 const void* lout, const void* scr) {
   const AdjLayout AL = make_adj_layout(c->p);
   const size_t sb = c->L.state_bytes, ab = AL.adj_bytes, cb = AL.total;
   const size_t fb = make_field_layout(c->p).total;
   if (overlap(lin, ab, lout, ab)) return fail(c, LBM_ERR_ARG, "adjoint input and output overlap");
-  if (overlap(lout, ab, state, sb) || overlap(scratch, cb, state, sb))
+  if (overlap(lout, ab, state, sb) || overlap(scr, cb, state, sb))
     return fail(c, LBM_ERR_ARG, "an adjoint buffer overlaps the state");
-  if (overlap(scratch, cb, lin, ab) || overlap(scratch, cb, lout, ab))
+  if (overlap(scr, cb, lin, ab) || overlap(scr, cb, lout, ab))
     return fail(c, LBM_ERR_ARG, "the scratch buffer overlaps an adjoint buffer");
-  if (fields && (overlap(fields, fb, lout, ab) || overlap(fields, fb, scratch, cb)))
+  if (fields && (overlap(fields, fb, lout, ab) || overlap(fields, fb, scr, cb)))
     return fail(c, LBM_ERR_ARG, "the fields buffer overlaps an adjoint output");
   return LBM_OK;
 }
@@ -978,6 +994,26 @@ lbm_status lbm_step_from(lbm_ctx* c, const void* d_src, void* d_dst, void* d_fie
 lbm_status lbm_moments(lbm_ctx* c, void* rr, void* rp, void* rn, void* u, void* cc) {
   if (!c) return LBM_ERR_ARG;
   DISPATCH(c, launch_moments, rr, rp, rn, u, cc);
+}
+
+lbm_status lbm_state_sums(lbm_ctx* c, const void* d_state, lbm_reductions* out) {
+  if (!c) return LBM_ERR_ARG;
+  if (!out) return fail(c, LBM_ERR_ARG, "out is NULL");
+  double row[5] = {0, 0, 0, 0, 0};
+  lbm_status s;
+  switch (c->p.precision) {
+    case LBM_FP64: s = launch_state_sums<0>(c, d_state, row); break;
+    case LBM_FP32: s = launch_state_sums<1>(c, d_state, row); break;
+    case LBM_FP16_DEV: s = launch_state_sums<2>(c, d_state, row); break;
+    default: s = launch_state_sums<3>(c, d_state, row); break;
+  }
+  if (s != LBM_OK) return s;
+  out->mass_r = row[0];
+  out->mass_p = row[1];
+  out->conversion = 0.0;
+  out->species_total = row[3];
+  out->nonfinite = row[4];
+  return LBM_OK;
 }
 
 lbm_status lbm_populations(lbm_ctx* c, void* fr, void* fp, void* g) {

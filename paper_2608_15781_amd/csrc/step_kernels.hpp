@@ -734,6 +734,38 @@ __global__ __launch_bounds__(kBlock, P >= 2 ? 5 : 1) void k_collide(StepArgs<P> 
 }
 
 // ---------------------------------------------------------------------------------------------
+// FP64 sums of a stored state S_t: m^r = sum a rho_s, m^p = sum b rho_s (eqs. reactant_mass,
+// product_mass), sum C_s and the non-finite count, with rho_s = sum_i f^m_i and C_s = sum_i g_i
+// the node's stored totals. Every stored population is pulled exactly once (by its neighbour,
+// or by the node itself through bounce-back), and the recolouring terms of a node cancel in
+// opposite pairs, so these are the colour masses and species total of level t. Slot 2
+// (conversion) is zero. One partial per workgroup, summed by k_finish_reduce.
+// ---------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_state_sums(StepArgs<P> A) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  double red5[5] = {0, 0, 0, 0, 0};
+  if (t < A.nfluid) {
+    R a, b;
+    unpack_frac(ld4(A.ain, t).x, a, b);
+    R s = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) s += Prec<P>::ld(A.fin[size_t(i) * A.ps + t], R(D::w(i)), A.inv_scale);
+    R C = 0;
+    if (A.species)
+#pragma unroll
+      for (int i = 0; i < 7; ++i) C += Prec<P>::ld(A.gin[size_t(i) * A.ps + t], R(D3Q7::w(i)), A.inv_gscale);
+    red5[0] = double(a) * double(s);
+    red5[1] = double(b) * double(s);
+    red5[3] = double(C);
+    red5[4] = (finite(s) && finite(a) && finite(C)) ? 0.0 : 1.0;
+  }
+  block_reduce5(red5, A.partials);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Expansion of the stored state to per-colour populations (lbm_populations).
 // ---------------------------------------------------------------------------------------------
 template <int P>
