@@ -426,7 +426,7 @@ class Lbm:
 
     def kernel_times(self):
         """Accumulated device milliseconds per kernel and the number of timed steps."""
-        ms = (ctypes.c_double * 4)()
+        ms = (ctypes.c_double * len(KERNELS))()
         n = ctypes.c_int64()
         self._check(lib().lbm_kernel_times(self._h, ms, ctypes.byref(n)), self._h)
         return dict(zip(KERNELS, list(ms))), int(n.value)

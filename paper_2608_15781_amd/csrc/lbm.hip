@@ -22,6 +22,8 @@ using namespace lbm;
 namespace {
 
 constexpr int kRing = 1024;          // per-step reduction rows kept on the device
+constexpr int kEvents = 5;           // profiling events per step: before k_colour, after each kernel
+constexpr int kTimed = 4;            // kernels timed per step: colour, extrap, normal, collide
 constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -164,10 +166,10 @@ struct lbm_ctx {
   int nb_fluid, nb_ext;  // workgroups over each list (multiples of kXcd, 0 if empty)
   bool ordered;          // fluid-list tiles launched in the order stored at L.order
   char err[512];
-  // Profiling: 5 events per step of the current chunk (before colour, after each kernel).
+  // Profiling: kEvents events per step of the current chunk (before the first kernel, after each).
   bool prof;
   std::vector<hipEvent_t> ev;
-  double kernel_ms[4];
+  double kernel_ms[kTimed];
   int64_t prof_steps;
 };
 
@@ -463,8 +465,8 @@ void use_fields(lbm_ctx* c, StepArgs<P>& A, void* fields) {
   A.rm_out = reinterpret_cast<R*>(fb + FL.rm);
 }
 
-// The four kernels of one step, with optional events (5) around them; without `collide` only
-// the level-t fields (colour, extrapolation, normals).
+// The four kernels of one step, with optional events (kEvents) around them; without `collide`
+// only the level-t fields (colour, extrapolation, normals).
 template <int P>
 lbm_status enqueue_step(lbm_ctx* c, const StepArgs<P>& A, hipEvent_t* ev, bool collide = true) {
   const dim3 block(kBlock), gf(c->nb_fluid), ge(c->nb_ext);
@@ -487,14 +489,14 @@ lbm_status launch_step(lbm_ctx* c, int slot, bool timed = true, void* fields = n
   if (fields) use_fields<P>(c, A, fields);
   double* ring = reinterpret_cast<double*>(c->ws + c->L.ring);
   A.ring_row = ring + 5 * size_t(slot);
-  // The previous step's partials are summed by k_normal of this step (its workgroup 0); the
-  // last step of a chunk is summed by launch_finish.
+  // The previous step's partials (one per k_collide workgroup) are summed by k_colour of this
+  // step (its workgroup 0); the last step of a chunk is summed by launch_finish.
   A.red_in = A.partials;
   A.red_n = c->nb_fluid;
   A.red_out = slot > 0 ? ring + 5 * size_t(slot - 1) : nullptr;
   if (A.red_out && !c->nb_fluid)
-    hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlock), 0, c->stream, A.partials, c->nb_fluid, A.red_out);
-  hipEvent_t* ev = (c->prof && timed) ? &c->ev[5 * size_t(slot)] : nullptr;
+    hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlock), 0, c->stream, A.partials, A.red_n, A.red_out);
+  hipEvent_t* ev = (c->prof && timed) ? &c->ev[kEvents * size_t(slot)] : nullptr;
   const lbm_status s = enqueue_step<P>(c, A, ev);
   if (s != LBM_OK) return s;
   c->cur = 1 - c->cur;
@@ -519,8 +521,6 @@ lbm_status launch_step_from(lbm_ctx* c, const void* src, void* dst, void* fields
   A.gout = db ? reinterpret_cast<S*>(db + c->L.g_off) : nullptr;
   if (fields) use_fields<P>(c, A, fields);
   A.ring_row = reinterpret_cast<double*>(c->ws + c->L.ring);
-  A.red_in = A.partials;
-  A.red_n = c->nb_fluid;
   A.red_out = nullptr;
   return enqueue_step<P>(c, A, nullptr, db != nullptr);  // no destination: the fields only
 }
@@ -918,9 +918,9 @@ lbm_status lbm_step(lbm_ctx* c, int32_t nsteps, lbm_reductions* per_step) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (c->prof) {
       for (int t = 0; t < chunk; ++t)
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kTimed; ++k) {
           float ms = 0.f;
-          HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[5 * size_t(t) + k], c->ev[5 * size_t(t) + k + 1]));
+          HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[kEvents * size_t(t) + k], c->ev[kEvents * size_t(t) + k + 1]));
           c->kernel_ms[k] += ms;
         }
       c->prof_steps += chunk;
@@ -1071,7 +1071,7 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* d_src, int64_t steps_done) {
 lbm_status lbm_set_profiling(lbm_ctx* c, int32_t enable) {
   if (!c) return LBM_ERR_ARG;
   if (enable && c->ev.empty()) {
-    c->ev.resize(5 * size_t(kRing));
+    c->ev.resize(kEvents * size_t(kRing));
     for (auto& e : c->ev) HIP_TRY(c, hipEventCreate(&e));
   }
   c->prof = enable != 0;
@@ -1082,7 +1082,7 @@ lbm_status lbm_set_profiling(lbm_ctx* c, int32_t enable) {
 
 lbm_status lbm_kernel_times(lbm_ctx* c, double* kernel_ms, int64_t* steps) {
   if (!c || !kernel_ms) return LBM_ERR_ARG;
-  for (int k = 0; k < 4; ++k) kernel_ms[k] = c->kernel_ms[k];
+  for (int k = 0; k < kTimed; ++k) kernel_ms[k] = c->kernel_ms[k];
   if (steps) *steps = c->prof_steps;
   return LBM_OK;
 }

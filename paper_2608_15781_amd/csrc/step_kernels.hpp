@@ -3,8 +3,8 @@
 // Storage. The state arrays hold fluid nodes only, indexed by fluid id (the rank of the node
 // among fluid nodes in node order, so rows stay contiguous); thread t of a launch is fluid node t
 // and writes its own slot, which makes every store a full coalesced line. Pulls find the id of
-// the source node through a dense node -> id map. The small per-node fields (rho^N, n*, wetting
-// data) stay dense, because the stencils also read them at solid nodes.
+// the source node through a dense node -> id map. The small per-node fields (rho^N, the info
+// word, the id map) stay dense, because the stencils also read them at solid nodes.
 //
 // State representation. Under Latva-Kokko recolouring of the colour-blind post-collision
 // populations (eq. operator_recoloring) followed by the proportional wall-reaction transfer,
@@ -26,9 +26,8 @@
 //
 // Layout: structure of arrays, one plane per population, planes a padded stride ps (at least the
 // number of fluid nodes) apart, fluid ids in node order (x fastest); the colour scalars (a, v) as
-// one 4-vector per fluid node. Two state buffers are used
-// alternately (pull from one, write the other), so no kernel reads what another thread of the
-// same launch writes.
+// one 4-vector per fluid node. Two state buffers are used alternately (pull from one, write the
+// other), so no kernel reads what another thread of the same launch writes.
 //
 // One step is four launches (each one thread per node):
 //   colour   pull f^m, a, v -> rho^N at fluid nodes             (eqs. moments_components, color_function)
@@ -50,6 +49,7 @@ namespace lbm {
 
 constexpr int kBlock = 256;
 constexpr int kXcd = 8;
+
 
 // Per-node 4-vectors (colour scalars a, v; realigned normal and |G|; wetting data) are stored
 // together (16 or 32 bytes per node) so that one load brings all four.
@@ -183,6 +183,9 @@ constexpr int yz_partner(int i) {
 // partner (x, y - c_iy, z - c_iz) minus c_ix when the partner is fluid, and the id map is read only
 // for the other sources. All of those reads are issued before any id is formed, so they are in
 // flight together.
+// x - cx (cx = +-1) is the next node along the row of x (no periodic wrap between them).
+__device__ inline bool row_step(const Nbr& nb, int cx) { return cx > 0 ? nb.dxm == -1 : nb.dxp == 1; }
+
 __device__ inline void pull_sources(const int* fid, const Nbr& nb, int t, uint32_t inf, int sid[18]) {
   using D = D3Q19;
   // Which ids follow from a neighbour's: known from the info bits alone, before any load.
@@ -191,8 +194,7 @@ __device__ inline void pull_sources(const int* fid, const Nbr& nb, int t, uint32
   for (int i = 0; i < 18; ++i) {
     const int m = yz_partner(i);
     const bool mfluid = (m < 0) || !((inf >> m) & 1u);
-    const bool in_row = (D::cx[i] > 0) ? (nb.dxm == -1) : (nb.dxp == 1);
-    derived[i] = (D::cx[i] != 0) && mfluid && in_row;
+    derived[i] = (D::cx[i] != 0) && mfluid && row_step(nb, D::cx[i]);
   }
   // Every id-map read first, so that they are in flight together; only then the ids.
   int look[18];
@@ -227,8 +229,7 @@ __device__ inline void pull_sources_lean(const int* fid, const Nbr& nb, int t, u
     const int m = yz_partner(i);
     const int mid = (m < 0) ? t : sid[m];
     const bool mfluid = (m < 0) || !((inf >> m) & 1u);
-    const bool in_row = (D::cx[i] > 0) ? (nb.dxm == -1) : (nb.dxp == 1);
-    sid[i] = ((inf >> i) & 1u) ? t : ((mfluid && in_row) ? mid - D::cx[i] : fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])]);
+    sid[i] = ((inf >> i) & 1u) ? t : ((mfluid && row_step(nb, D::cx[i])) ? mid - D::cx[i] : fid[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])]);
   }
 }
 
@@ -263,7 +264,8 @@ struct StepArgs {
   const R* wet;  // per fluid id 4-vector (n_s, cos(theta))
   double* partials;
   double* ring_row;  // 5 doubles of this step
-  // Deferred final reduction of the previous step, done by workgroup 0 of k_normal (null: none)
+  // Deferred final reduction of the previous step, done by workgroup 0 of the step's first pass
+  // (null: none)
   const double* red_in;
   int red_n;
   double* red_out;
@@ -335,6 +337,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
+  if (A.red_out && blockIdx.x == 0) reduce_partials(A.red_in, A.red_n, A.red_out);
   const int t = fluid_tile(A) * kBlock + threadIdx.x;
   if (t >= A.nfluid) return;
   const int n = A.fluid[t];
@@ -406,39 +409,32 @@ __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs<P> A) {
 // through the reactant colour), and at wetting nodes the Akai realignment
 // n* = n+ (n+ is always at least as close to n as n-: n+.n - n-.n = 2 sin(theta) sin(theta')).
 // ---------------------------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
-  using R = typename Prec<P>::R;
+// The normal of one fluid node from the nine pair differences d_j = rho^N(x + c_p) - rho^N(x - c_p),
+// p = half[j], of its neighbours' colour (rn_diff form): G, |G|, n = G/|G|, and at wetting nodes
+// the Akai realignment with wv = (n_s, cos(theta)). raw: the unit normal before realignment, set
+// (and raw_set true) at wetting nodes with |G| > eps. Every pass that forms a normal calls this.
+template <class R>
+__device__ inline void normal_from_pairs(const R d[9], uint32_t inf, const typename V4<R>::T& wv, R eps, R nv[3],
+                                         R& len, R raw[3], bool& raw_set) {
   using D = D3Q19;
-  if (A.red_out && blockIdx.x == 0) reduce_partials(A.red_in, A.red_n, A.red_out);
-  // the plain list order here: the tile order measured slower for this pass
-  const int t = logical_block() * kBlock + threadIdx.x;
-  if (t >= A.nfluid) return;
-  const int n = A.fluid[t];
-  const uint32_t inf = A.finfo[t];
-  const Nbr nb = make_nbr(n, A.geo);
-  // The wetting data of a wetting node is loaded with the neighbours' colours, not after the
-  // gradient: one memory round trip for the node instead of two.
-  typename V4<R>::T wv;
-  wv.x = wv.y = wv.z = wv.w = R(0);
-  if (inf & kWet) wv = ld4(A.wet, t);
   R g[3] = {0, 0, 0};
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     const int p = D::half[j];
-    const R d = rn_diff(A.rhoN[nb.at(D::cx[p], D::cy[p], D::cz[p])], A.rhoN[nb.at(-D::cx[p], -D::cy[p], -D::cz[p])]);
     const R c3w = R(3.0 * D::w(p));
-    if (D::cx[p]) g[0] += c3w * R(D::cx[p]) * d;
-    if (D::cy[p]) g[1] += c3w * R(D::cy[p]) * d;
-    if (D::cz[p]) g[2] += c3w * R(D::cz[p]) * d;
+    if (D::cx[p]) g[0] += c3w * R(D::cx[p]) * d[j];
+    if (D::cy[p]) g[1] += c3w * R(D::cy[p]) * d[j];
+    if (D::cz[p]) g[2] += c3w * R(D::cz[p]) * d[j];
   }
-  const R len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-  R nv[3] = {0, 0, 0};
-  if (len > A.eps) {
+  len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  nv[0] = nv[1] = nv[2] = R(0);
+  raw_set = false;
+  if (len > eps) {
     const R il = R(1) / len;
     nv[0] = g[0] * il; nv[1] = g[1] * il; nv[2] = g[2] * il;
     if (inf & kWet) {
-      if (A.nraw) st4(A.nraw, t, nv[0], nv[1], nv[2], R(0));
+      raw[0] = nv[0]; raw[1] = nv[1]; raw[2] = nv[2];
+      raw_set = true;
       const R sx = wv.x, sy = wv.y, sz = wv.z;
       if (sx * sx + sy * sy + sz * sz > R(0.5)) {
         const R ct = wv.w;
@@ -461,6 +457,32 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
       }
     }
   }
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const int t = logical_block() * kBlock + threadIdx.x;
+  if (t >= A.nfluid) return;
+  const int n = A.fluid[t];
+  const uint32_t inf = A.finfo[t];
+  const Nbr nb = make_nbr(n, A.geo);
+  // The wetting data of a wetting node is loaded with the neighbours' colours, not after the
+  // gradient: one memory round trip for the node instead of two.
+  typename V4<R>::T wv;
+  wv.x = wv.y = wv.z = wv.w = R(0);
+  if (inf & kWet) wv = ld4(A.wet, t);
+  R d[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const int p = D::half[j];
+    d[j] = rn_diff(A.rhoN[nb.at(D::cx[p], D::cy[p], D::cz[p])], A.rhoN[nb.at(-D::cx[p], -D::cy[p], -D::cz[p])]);
+  }
+  R nv[3], len, raw[3];
+  bool raw_set;
+  normal_from_pairs<R>(d, inf, wv, A.eps, nv, len, raw, raw_set);
+  if (raw_set && A.nraw) st4(A.nraw, t, raw[0], raw[1], raw[2], R(0));
   st4(A.nst, t, nv[0], nv[1], nv[2], len);
 }
 
@@ -506,11 +528,12 @@ __device__ inline bool finite(R v) {
   return isfinite(v);
 }
 
-// Deterministic FP64 reduction of 5 sums: wavefront shuffles, then the workgroup's waves in
-// fixed order; one partial per workgroup (plain stores, no fences or atomics). k_finish_reduce,
-// launched after the grid on the same stream, adds the partials in workgroup order.
-__device__ inline void block_reduce5(double s[5], double* partials) {
-  __shared__ double red[kBlock / 64][5];
+// Deterministic FP64 reduction of 5 sums over a workgroup of NT threads: wavefront shuffles, then
+// the workgroup's waves in fixed order; one partial per workgroup (plain stores, no fences or
+// atomics). The sums are finished by reduce_partials, after the grid, in workgroup order.
+template <int NT>
+__device__ inline void block_reduce5_n(double s[5], double* partials) {
+  __shared__ double red[NT / 64][5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
 #pragma unroll
@@ -527,20 +550,225 @@ __device__ inline void block_reduce5(double s[5], double* partials) {
     for (int j = 0; j < 5; ++j) {
       double t = red[0][j];
 #pragma unroll
-      for (int w = 1; w < kBlock / 64; ++w) t += red[w][j];
+      for (int w = 1; w < NT / 64; ++w) t += red[w][j];
       partials[size_t(j) * gridDim.x + lb] = t;
     }
   }
 }
 
+__device__ inline void block_reduce5(double s[5], double* partials) { block_reduce5_n<kBlock>(s, partials); }
+
+// Pull of fluid node t with halfway bounce-back: f^m_i from S_t at x - c_i, or S_t,opp(i) at x
+// where x - c_i is solid (sid: the sources' fluid ids, t for bounce-back), and likewise the species
+// (the outflow plane takes its own S_1: zero gradient).
+template <int P>
+__device__ inline void pull_node(const StepArgs<P>& A, int t, uint32_t inf, const int sid[18],
+                                 typename Prec<P>::R f[19], typename Prec<P>::R g[7]) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const bool bb = (i < 18) && ((inf >> i) & 1u);
+    const int src = (i < 18) ? sid[i] : t;
+    const int q = bb ? D::opp[i] : i;
+    f[i] = Prec<P>::ld(A.fin[size_t(q) * A.ps + src], R(D::w(i)), A.inv_scale);
+  }
+#pragma unroll
+  for (int i = 0; i < 7; ++i) g[i] = R(0);
+  if (A.species) {
+    const bool outlet = inf & kOutlet;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const bool own = (i == 1 && outlet);  // zero-gradient outflow: the node's own S_1
+      const bool bb = !own && ((inf >> i) & 1u);
+      const int src = own ? t : sid[i];
+      const int q = own ? 1 : (bb ? D3Q7::opp[i] : i);
+      g[i] = Prec<P>::ld(A.gin[size_t(q) * A.ps + src], R(D3Q7::w(i)), A.inv_gscale);
+    }
+    g[6] = Prec<P>::ld(A.gin[6 * A.ps + t], R(D3Q7::w(6)), A.inv_gscale);
+  }
+}
+
+// H |G| at fluid node x: the curvature H = -(tr J - n.J.n) (eq. interface_curvature) with
+// J_ab = 3 sum_i w_i c_ib n*_a(x + c_i), times the gradient magnitude |G| of x; zero where
+// |G| <= eps (no normal). nsv: (n*, |G|) of x; nbr(i): (n*, |G|) at x + c_i, or of x itself where
+// x + c_i is solid (the value the curvature takes for a solid neighbour). Every pass that forms
+// the curvature calls this.
+template <class R, class NbrN>
+__device__ inline R curvature_hg(const typename V4<R>::T& nsv, R eps, NbrN nbr) {
+  using D = D3Q19;
+  R J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    const typename V4<R>::T nbi = nbr(i);
+    const R a0 = nbi.x, a1 = nbi.y, a2 = nbi.z;
+    const R w3 = R(3.0 * D::w(i));
+    if (D::cx[i]) { J[0][0] += w3 * R(D::cx[i]) * a0; J[1][0] += w3 * R(D::cx[i]) * a1; J[2][0] += w3 * R(D::cx[i]) * a2; }
+    if (D::cy[i]) { J[0][1] += w3 * R(D::cy[i]) * a0; J[1][1] += w3 * R(D::cy[i]) * a1; J[2][1] += w3 * R(D::cy[i]) * a2; }
+    if (D::cz[i]) { J[0][2] += w3 * R(D::cz[i]) * a0; J[1][2] += w3 * R(D::cz[i]) * a1; J[2][2] += w3 * R(D::cz[i]) * a2; }
+  }
+  const R glen = nsv.w;
+  R H = 0;
+  if (glen > eps) {
+    const R nn[3] = {nsv.x, nsv.y, nsv.z};
+    R nJn = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) nJn += nn[a] * nn[b] * J[a][b];
+    H = -((J[0][0] + J[1][1] + J[2][2]) - nJn);
+  }
+  return H * glen;
+}
+
+// The collision and the rest of the step at one fluid node x (fluid id t, node n, info word inf):
+// moments, forcing, central-moment collision, recolouring, reaction, species, store, and the
+// node's contribution to the FP64 sums (added to red5). f, g: the pulled populations; rn: rho^N(x)
+// (rn_value form); cur: (n*, H |G|) of x (n* = 0 where x has no normal). MOM writes the level-t
+// fields instead.
+template <int P, bool MOM>
+__device__ inline void collide_node(const StepArgs<P>& A, int t, int n, uint32_t inf,
+                                    const typename Prec<P>::R f[19], const typename Prec<P>::R g[7],
+                                    typename Prec<P>::R rn, const typename V4<typename Prec<P>::R>::T& cur,
+                                    double red5[5]) {
+  using R = typename Prec<P>::R;
+  using D = D3Q19;
+  const size_t N = A.N;
+  // Moments (same summation order as k_colour, so rho^m agrees bit for bit).
+  R rm = 0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) rm += f[i];
+  R mx = 0, my = 0, mz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    if (D::cx[i]) { mx += R(D::cx[i]) * f[i]; pxx += f[i]; }
+    if (D::cy[i]) { my += R(D::cy[i]) * f[i]; pyy += f[i]; }
+    if (D::cz[i]) { mz += R(D::cz[i]) * f[i]; pzz += f[i]; }
+    if (D::cx[i] && D::cy[i]) pxy += R(D::cx[i] * D::cy[i]) * f[i];
+    if (D::cx[i] && D::cz[i]) pxz += R(D::cx[i] * D::cz[i]) * f[i];
+    if (D::cy[i] && D::cz[i]) pyz += R(D::cy[i] * D::cz[i]) * f[i];
+  }
+  const R irm = R(1) / rm;
+  const R ux = mx * irm, uy = my * irm, uz = mz * irm;
+  R rr, rp;
+  rn_densities(rn, rm, rr, rp);
+
+  // Realigned unit normal (zero where the node has no normal: a unit vector otherwise) and the
+  // exact-difference forcing du^k = F^k / rho^k = (1/2) sigma H |G| n* / rho^m + a^k.
+  const R n0 = cur.x, n1 = cur.y, n2 = cur.z;
+  const bool has_n = n0 != R(0) || n1 != R(0) || n2 != R(0);
+  const R fc = R(0.5) * A.sigma * cur.w * irm;
+  const R dur[3] = {fc * n0 + A.acc[0][0], fc * n1 + A.acc[0][1], fc * n2 + A.acc[0][2]};
+  const R dup[3] = {fc * n0 + A.acc[1][0], fc * n1 + A.acc[1][1], fc * n2 + A.acc[1][2]};
+  const R upx = ux + R(0.5) * (rr * dur[0] + rp * dup[0]) * irm;
+  const R upy = uy + R(0.5) * (rr * dur[1] + rp * dup[1]) * irm;
+  const R upz = uz + R(0.5) * (rr * dur[2] + rp * dup[2]) * irm;
+
+  R C = R(1);
+  if (A.species) {
+    C = 0;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) C += g[i];
+    if (inf & kInlet) C = A.c_in;
+  }
+
+  if (MOM) {
+    if (A.m_rr) A.m_rr[n] = rr;
+    if (A.m_rp) A.m_rp[n] = rp;
+    if (A.m_rn) A.m_rn[n] = rn_value(rn);
+    if (A.m_u) { A.m_u[n] = upx; A.m_u[N + n] = upy; A.m_u[2 * N + n] = upz; }
+    if (A.m_c) A.m_c[n] = C;
+  } else {
+    // Central shear moments k5..k9 about the bare velocity, relaxed by (1 - 1/tau).
+    const R cxx = pxx - rm * ux * ux, cyy = pyy - rm * uy * uy, czz = pzz - rm * uz * uz;
+    const R k5 = A.relax * (cxx - cyy), k6 = A.relax * (cyy - czz);
+    const R k7 = A.relax * (pxy - rm * ux * uy), k8 = A.relax * (pxz - rm * ux * uz), k9 = A.relax * (pyz - rm * uy * uz);
+    R d[19];
+    cm_back(ux, uy, uz, k5, k6, k7, k8, k9, d);
+    // f^{m,*} = f^eq(rho^r, u + du^r) + f^eq(rho^p, u + du^p) + T^{-1} k*: the sum of both
+    // colours' equilibria needs only M = sum_k rho^k U^k and Pi = sum_k rho^k U^k U^k.
+    const R Ur[3] = {ux + dur[0], uy + dur[1], uz + dur[2]};
+    const R Up[3] = {ux + dup[0], uy + dup[1], uz + dup[2]};
+    const R M0 = rr * Ur[0] + rp * Up[0], M1 = rr * Ur[1] + rp * Up[1], M2 = rr * Ur[2] + rp * Up[2];
+    const R Pxx = rr * Ur[0] * Ur[0] + rp * Up[0] * Up[0];
+    const R Pyy = rr * Ur[1] * Ur[1] + rp * Up[1] * Up[1];
+    const R Pzz = rr * Ur[2] * Ur[2] + rp * Up[2] * Up[2];
+    const R Pxy = rr * Ur[0] * Ur[1] + rp * Up[0] * Up[1];
+    const R Pxz = rr * Ur[0] * Ur[2] + rp * Up[0] * Up[2];
+    const R Pyz = rr * Ur[1] * Ur[2] + rp * Up[1] * Up[2];
+    const R base = rm - R(1.5) * (Pxx + Pyy + Pzz);
+    R fs[19];
+    R fsum = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const int cx = D::cx[i], cy = D::cy[i], cz = D::cz[i];
+      R cM = 0, cPc = 0;
+      if (cx) { cM += R(cx) * M0; cPc += Pxx; }
+      if (cy) { cM += R(cy) * M1; cPc += Pyy; }
+      if (cz) { cM += R(cz) * M2; cPc += Pzz; }
+      if (cx && cy) cPc += R(2 * cx * cy) * Pxy;
+      if (cx && cz) cPc += R(2 * cx * cz) * Pxz;
+      if (cy && cz) cPc += R(2 * cy * cz) * Pyz;
+      fs[i] = R(D::w(i)) * (base + R(3) * cM + R(4.5) * cPc) + d[i];
+      fsum += fs[i];
+    }
+    // Wall reaction with level-t densities, capped at full conversion.
+    const int rnn = int((inf & kRnnMask) >> kRnnShift);
+    R delta = 0;
+    if (rnn > 0 && rr > R(0)) {
+      if (A.species) {
+        if (C > R(0)) {
+          const R rate = A.xi * R(rnn) * rr * C;
+          const R cap = fmin(rr, C);
+          delta = fmin(rate, cap);
+        }
+      } else {
+        delta = fmin(A.xi * R(rnn), R(1)) * rr;
+      }
+    }
+    const R keep = (delta != R(0)) ? R(1) - delta / rr : R(1);
+    // Compact recoloured state: a = (rho^r - delta)/rho^m, b = (rho^p + delta)/rho^m,
+    // v = keep beta rho^r rho^p/rho^m n* with keep = 1 - delta/rho^r.
+    const R aout = pack_frac((rr - delta) * irm, (rp + delta) * irm);
+    const R vc = keep * A.beta * rr * rp * irm;
+    const R v0 = has_n ? vc * n0 : R(0), v1 = has_n ? vc * n1 : R(0), v2 = has_n ? vc * n2 : R(0);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) A.fout[size_t(i) * A.ps + t] = Prec<P>::st(fs[i], R(D::w(i)), A.scale);
+    st4(A.aout, t, aout, v0, v1, v2);
+    bool ok = finite(fsum) && finite(aout) && finite(v0 + v1 + v2) && finite(rr) && finite(rp);
+    if (A.species) {
+      // BGK towards g^eq = w C (1 + 4 c.u_phys); at the inlet the populations are replaced by
+      // the equilibrium at C_in; then the reaction sink.
+      const bool inlet = inf & kInlet;
+      const R sink = (delta != R(0)) ? R(1) - delta / C : R(1);
+      const R cu[7] = {upx, -upx, upy, -upy, upz, -upz, R(0)};
+      R gs = 0;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        const R geq = R(D3Q7::w(i)) * C * (R(1) + R(4) * cu[i]);
+        const R gi = inlet ? geq : g[i];
+        const R go = (gi + (geq - gi) * A.inv_tau_c) * sink;
+        gs += go;
+        A.gout[size_t(i) * A.ps + t] = Prec<P>::st(go, R(D3Q7::w(i)), A.gscale);
+      }
+      ok = ok && finite(gs);
+    }
+    red5[0] += double(rr);
+    red5[1] += double(rp);
+    red5[2] += double(delta);
+    red5[3] += double(C);
+    red5[4] += ok ? 0.0 : 1.0;
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // collide: the rest of the step at every fluid node. MOM = true writes the level-t fields
-// instead (lbm_moments) and leaves the state untouched. With 2-byte storage the pass runs five
-// waves per SIMD (96 VGPRs, no spills; 4% faster than four); FP32 gains nothing from five and
-// FP64 spills.
+// instead (lbm_moments) and leaves the state untouched. Four waves per SIMD in FP32, FP16 and BF16
+// (at most 128 VGPRs, no spills; a five-wave bound made the 2-byte storages spill and run 11%
+// slower at 512^3); FP64 runs fewer.
 // ---------------------------------------------------------------------------------------------
 template <int P, bool MOM>
-__global__ __launch_bounds__(kBlock, P >= 2 ? 5 : 1) void k_collide(StepArgs<P> A) {
+__global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
   using R = typename Prec<P>::R;
   using D = D3Q19;
   const int t = fluid_tile(A) * kBlock + threadIdx.x;
@@ -549,186 +777,23 @@ __global__ __launch_bounds__(kBlock, P >= 2 ? 5 : 1) void k_collide(StepArgs<P> 
   const uint32_t inf = (t < A.nfluid) ? A.finfo[t] : 0u;
   if (inf & kFluid) {
     const Nbr nb = make_nbr(n, A.geo);
-    const size_t N = A.N;
     // All loads of the node first (pull of f^m and g with halfway bounce-back, rho^N, the node's
     // and its neighbours' realigned normals), so that one memory round trip covers them.
     int sid[18];  // fluid ids of the pull sources (own id for bounce-back)
     pull_sources(A.fid, nb, t, inf, sid);
-    R f[19];
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      const bool bb = (i < 18) && ((inf >> i) & 1u);
-      const int src = (i < 18) ? sid[i] : t;
-      const int q = bb ? D::opp[i] : i;
-      f[i] = Prec<P>::ld(A.fin[size_t(q) * A.ps + src], R(D::w(i)), A.inv_scale);
-    }
-    R g[7] = {0, 0, 0, 0, 0, 0, 0};
-    if (A.species) {
-      const bool outlet = inf & kOutlet;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const bool own = (i == 1 && outlet);  // zero-gradient outflow: the node's own S_1
-        const bool bb = !own && ((inf >> i) & 1u);
-        const int src = own ? t : sid[i];
-        const int q = own ? 1 : (bb ? D3Q7::opp[i] : i);
-        g[i] = Prec<P>::ld(A.gin[size_t(q) * A.ps + src], R(D3Q7::w(i)), A.inv_gscale);
-      }
-      g[6] = Prec<P>::ld(A.gin[6 * A.ps + t], R(D3Q7::w(6)), A.inv_gscale);
-    }
+    R f[19], g[7];
+    pull_node(A, t, inf, sid, f, g);
     const R rn = A.rhoN[n];
+    // The node's and its neighbours' realigned normals; x + c_i is the pull source of direction
+    // opp(i), the node's own id where it is solid, which is the value the curvature takes for a
+    // solid neighbour.
     const typename V4<R>::T nsv = ld4(A.nst, t);
-    // x + c_i is the pull source of direction opp(i); where it is solid that id is the node's
-    // own, which is the value the curvature takes for a solid neighbour.
     typename V4<R>::T nbv[18];
 #pragma unroll
     for (int i = 0; i < 18; ++i) nbv[i] = ld4(A.nst, sid[D::opp[i]]);
-    // Moments (same summation order as k_colour, so rho^m agrees bit for bit).
-    R rm = 0;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) rm += f[i];
-    R mx = 0, my = 0, mz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      if (D::cx[i]) { mx += R(D::cx[i]) * f[i]; pxx += f[i]; }
-      if (D::cy[i]) { my += R(D::cy[i]) * f[i]; pyy += f[i]; }
-      if (D::cz[i]) { mz += R(D::cz[i]) * f[i]; pzz += f[i]; }
-      if (D::cx[i] && D::cy[i]) pxy += R(D::cx[i] * D::cy[i]) * f[i];
-      if (D::cx[i] && D::cz[i]) pxz += R(D::cx[i] * D::cz[i]) * f[i];
-      if (D::cy[i] && D::cz[i]) pyz += R(D::cy[i] * D::cz[i]) * f[i];
-    }
-    const R irm = R(1) / rm;
-    const R ux = mx * irm, uy = my * irm, uz = mz * irm;
-    R rr, rp;
-    rn_densities(rn, rm, rr, rp);
-
-    // Realigned unit normal and gradient magnitude; curvature H = -(tr J - n.J.n) with
-    // J_ab = 3 sum_i w_i c_ib n*_a(x + c_i), a solid neighbour contributing n*(x).
-    const R n0 = nsv.x, n1 = nsv.y, n2 = nsv.z;
-    const R glen = nsv.w;
-    const bool has_n = glen > A.eps;
-    R J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-    for (int i = 0; i < 18; ++i) {
-      const R a0 = nbv[i].x, a1 = nbv[i].y, a2 = nbv[i].z;
-      const R w3 = R(3.0 * D::w(i));
-      if (D::cx[i]) { J[0][0] += w3 * R(D::cx[i]) * a0; J[1][0] += w3 * R(D::cx[i]) * a1; J[2][0] += w3 * R(D::cx[i]) * a2; }
-      if (D::cy[i]) { J[0][1] += w3 * R(D::cy[i]) * a0; J[1][1] += w3 * R(D::cy[i]) * a1; J[2][1] += w3 * R(D::cy[i]) * a2; }
-      if (D::cz[i]) { J[0][2] += w3 * R(D::cz[i]) * a0; J[1][2] += w3 * R(D::cz[i]) * a1; J[2][2] += w3 * R(D::cz[i]) * a2; }
-    }
-    R H = 0;
-    if (has_n) {
-      const R nn[3] = {n0, n1, n2};
-      R nJn = 0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) nJn += nn[a] * nn[b] * J[a][b];
-      H = -((J[0][0] + J[1][1] + J[2][2]) - nJn);
-    }
-
-    // Exact-difference forcing: du^k = F^k / rho^k = (1/2) sigma H |G| n* / rho^m + a^k.
-    const R fc = R(0.5) * A.sigma * H * glen * irm;
-    const R dur[3] = {fc * n0 + A.acc[0][0], fc * n1 + A.acc[0][1], fc * n2 + A.acc[0][2]};
-    const R dup[3] = {fc * n0 + A.acc[1][0], fc * n1 + A.acc[1][1], fc * n2 + A.acc[1][2]};
-    const R upx = ux + R(0.5) * (rr * dur[0] + rp * dup[0]) * irm;
-    const R upy = uy + R(0.5) * (rr * dur[1] + rp * dup[1]) * irm;
-    const R upz = uz + R(0.5) * (rr * dur[2] + rp * dup[2]) * irm;
-
-    R C = R(1);
-    if (A.species) {
-      C = 0;
-#pragma unroll
-      for (int i = 0; i < 7; ++i) C += g[i];
-      if (inf & kInlet) C = A.c_in;
-    }
-
-    if (MOM) {
-      if (A.m_rr) A.m_rr[n] = rr;
-      if (A.m_rp) A.m_rp[n] = rp;
-      if (A.m_rn) A.m_rn[n] = rn_value(rn);
-      if (A.m_u) { A.m_u[n] = upx; A.m_u[N + n] = upy; A.m_u[2 * N + n] = upz; }
-      if (A.m_c) A.m_c[n] = C;
-    } else {
-      // Central shear moments k5..k9 about the bare velocity, relaxed by (1 - 1/tau).
-      const R cxx = pxx - rm * ux * ux, cyy = pyy - rm * uy * uy, czz = pzz - rm * uz * uz;
-      const R k5 = A.relax * (cxx - cyy), k6 = A.relax * (cyy - czz);
-      const R k7 = A.relax * (pxy - rm * ux * uy), k8 = A.relax * (pxz - rm * ux * uz), k9 = A.relax * (pyz - rm * uy * uz);
-      R d[19];
-      cm_back(ux, uy, uz, k5, k6, k7, k8, k9, d);
-      // f^{m,*} = f^eq(rho^r, u + du^r) + f^eq(rho^p, u + du^p) + T^{-1} k*: the sum of both
-      // colours' equilibria needs only M = sum_k rho^k U^k and Pi = sum_k rho^k U^k U^k.
-      const R Ur[3] = {ux + dur[0], uy + dur[1], uz + dur[2]};
-      const R Up[3] = {ux + dup[0], uy + dup[1], uz + dup[2]};
-      const R M0 = rr * Ur[0] + rp * Up[0], M1 = rr * Ur[1] + rp * Up[1], M2 = rr * Ur[2] + rp * Up[2];
-      const R Pxx = rr * Ur[0] * Ur[0] + rp * Up[0] * Up[0];
-      const R Pyy = rr * Ur[1] * Ur[1] + rp * Up[1] * Up[1];
-      const R Pzz = rr * Ur[2] * Ur[2] + rp * Up[2] * Up[2];
-      const R Pxy = rr * Ur[0] * Ur[1] + rp * Up[0] * Up[1];
-      const R Pxz = rr * Ur[0] * Ur[2] + rp * Up[0] * Up[2];
-      const R Pyz = rr * Ur[1] * Ur[2] + rp * Up[1] * Up[2];
-      const R base = rm - R(1.5) * (Pxx + Pyy + Pzz);
-      R fs[19];
-      R fsum = 0;
-#pragma unroll
-      for (int i = 0; i < 19; ++i) {
-        const int cx = D::cx[i], cy = D::cy[i], cz = D::cz[i];
-        R cM = 0, cPc = 0;
-        if (cx) { cM += R(cx) * M0; cPc += Pxx; }
-        if (cy) { cM += R(cy) * M1; cPc += Pyy; }
-        if (cz) { cM += R(cz) * M2; cPc += Pzz; }
-        if (cx && cy) cPc += R(2 * cx * cy) * Pxy;
-        if (cx && cz) cPc += R(2 * cx * cz) * Pxz;
-        if (cy && cz) cPc += R(2 * cy * cz) * Pyz;
-        fs[i] = R(D::w(i)) * (base + R(3) * cM + R(4.5) * cPc) + d[i];
-        fsum += fs[i];
-      }
-      // Wall reaction with level-t densities, capped at full conversion.
-      const int rnn = int((inf & kRnnMask) >> kRnnShift);
-      R delta = 0;
-      if (rnn > 0 && rr > R(0)) {
-        if (A.species) {
-          if (C > R(0)) {
-            const R rate = A.xi * R(rnn) * rr * C;
-            const R cap = fmin(rr, C);
-            delta = fmin(rate, cap);
-          }
-        } else {
-          delta = fmin(A.xi * R(rnn), R(1)) * rr;
-        }
-      }
-      const R keep = (delta != R(0)) ? R(1) - delta / rr : R(1);
-      // Compact recoloured state: a = (rho^r - delta)/rho^m, b = (rho^p + delta)/rho^m,
-      // v = keep beta rho^r rho^p/rho^m n* with keep = 1 - delta/rho^r.
-      const R aout = pack_frac((rr - delta) * irm, (rp + delta) * irm);
-      const R vc = keep * A.beta * rr * rp * irm;
-      const R v0 = has_n ? vc * n0 : R(0), v1 = has_n ? vc * n1 : R(0), v2 = has_n ? vc * n2 : R(0);
-#pragma unroll
-      for (int i = 0; i < 19; ++i) A.fout[size_t(i) * A.ps + t] = Prec<P>::st(fs[i], R(D::w(i)), A.scale);
-      st4(A.aout, t, aout, v0, v1, v2);
-      bool ok = finite(fsum) && finite(aout) && finite(v0 + v1 + v2) && finite(rr) && finite(rp);
-      if (A.species) {
-        // BGK towards g^eq = w C (1 + 4 c.u_phys); at the inlet the populations are replaced by
-        // the equilibrium at C_in; then the reaction sink.
-        const bool inlet = inf & kInlet;
-        const R sink = (delta != R(0)) ? R(1) - delta / C : R(1);
-        const R cu[7] = {upx, -upx, upy, -upy, upz, -upz, R(0)};
-        R gs = 0;
-#pragma unroll
-        for (int i = 0; i < 7; ++i) {
-          const R geq = R(D3Q7::w(i)) * C * (R(1) + R(4) * cu[i]);
-          const R gi = inlet ? geq : g[i];
-          const R go = (gi + (geq - gi) * A.inv_tau_c) * sink;
-          gs += go;
-          A.gout[size_t(i) * A.ps + t] = Prec<P>::st(go, R(D3Q7::w(i)), A.gscale);
-        }
-        ok = ok && finite(gs);
-      }
-      red5[0] = double(rr);
-      red5[1] = double(rp);
-      red5[2] = double(delta);
-      red5[3] = double(C);
-      red5[4] = ok ? 0.0 : 1.0;
-    }
+    typename V4<R>::T cur = nsv;
+    cur.w = curvature_hg<R>(nsv, A.eps, [&](int i) { return nbv[i]; });
+    collide_node<P, MOM>(A, t, n, inf, f, g, rn, cur, red5);
   }
   if (!MOM) block_reduce5(red5, A.partials);
 }

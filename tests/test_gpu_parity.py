@@ -18,8 +18,8 @@ FP32_TOL = 2e-4
 HALF_TOL = 2e-2
 BF16_TOL = 1e-1
 # FP32 on the 48^3 crop of the benchmark mask after 2000 steps (see that test)
-CROP_FP32_TOL = 1e-3
-CROP_FP32_U_L2 = 5e-2
+CROP_FP32_TOL = 3e-3
+CROP_FP32_U_L2 = 2e-3
 
 
 def _rel(a, b):
@@ -487,7 +487,10 @@ def test_bench_mask_crop48_2000_steps(core, oracle_mod):
     gas colour is a trace produced at the walls), 2000 steps, the horizon of the 128^3 FP32
     workload. FP64 within FP64_TOL in every field, population and per-step sum after 200 and
     after 2000 steps. FP32 after 2000 steps: densities, colour function, species and populations
-    within CROP_FP32_TOL (max norm), the velocity in relative L2 within CROP_FP32_U_L2."""
+    within CROP_FP32_TOL (max norm), the velocity in relative L2 within CROP_FP32_U_L2. FP32
+    rounding (6e-8 relative per operation) grows along the interfaces over the horizon: measured
+    8.5e-4 on rho^N, 4.4e-4 on the populations and 1.5e-4 on the velocity; the bounds leave a
+    factor of 3.5 and 13."""
     from paper_2608_15781_amd import inputs
 
     n, T1, T = 48, 200, 2000
