@@ -256,6 +256,21 @@ int64_t lbm_steps_done(const lbm_ctx* ctx);
 /* Releases the context (host memory only; the workspace belongs to the caller). */
 void lbm_free(lbm_ctx* ctx);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): lbm_adjoint_step without the d_scratch argument. Its
+ * scratch is a fixed array of lbm_adjoint_static_scratch_bytes() (64 MiB) inside the library,
+ * one per device, held until the process ends; the call allocates nothing. Same arguments,
+ * results (bit for bit) and errors as lbm_adjoint_step, plus LBM_ERR_ARG when the problem needs
+ * more scratch than the array holds (lbm_adjoint_bytes reports the need: about 8 r N + 12 r F
+ * bytes for N nodes, F fluid nodes, r = 4 in FP32/FP16/BF16 and 8 in FP64; the 96^3 porous
+ * workload fits in FP32, not in FP64) and LBM_ERR_HIP if the array's device address cannot be
+ * resolved. Every call on one device shares that device's array and leaves its contents behind:
+ * calls that overlap in time on one device (two streams, two threads) race and must be ordered
+ * by the caller; every value a call reads from the array it has written first. */
+lbm_status lbm_adjoint_step_static(lbm_ctx* ctx, const void* d_state, const void* d_adj_in, void* d_adj_out,
+                                   double* d_grad_theta, double* d_grad_xi);
+size_t lbm_adjoint_static_scratch_bytes(void);
+
 /* Message of the last error on this context (context-owned storage), or with ctx NULL of the
  * last failed call without a context on the calling thread (thread-local storage); never NULL. */
 const char* lbm_last_error(const lbm_ctx* ctx);

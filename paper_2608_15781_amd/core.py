@@ -21,7 +21,8 @@ EXPORTED = ["lbm_version", "lbm_workspace_bytes", "lbm_state_bytes", "lbm_init",
             "lbm_populations", "lbm_geometry", "lbm_state_layout", "lbm_get_state", "lbm_set_state",
             "lbm_set_profiling", "lbm_kernel_times", "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step",
             "lbm_steps_done", "lbm_free", "lbm_last_error", "lbm_fields_bytes", "lbm_step_fields",
-            "lbm_adjoint_step_fields", "lbm_step_from", "lbm_state_sums"]
+            "lbm_adjoint_step_fields", "lbm_step_from", "lbm_state_sums", "lbm_adjoint_step_static",
+            "lbm_adjoint_static_scratch_bytes"]
 KERNELS = ("colour", "extrap", "normal", "collide")
 
 
@@ -73,6 +74,9 @@ def lib():
         L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lbm_populations.argtypes = [vp, vp, vp, vp]
         L.lbm_state_sums.argtypes = [vp, vp, vp]
+        L.lbm_adjoint_step_static.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.lbm_adjoint_static_scratch_bytes.argtypes = []
+        L.lbm_adjoint_static_scratch_bytes.restype = sz
         L.lbm_geometry.argtypes = [vp, vp, vp]
         L.lbm_get_state.argtypes = [vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, i64]
@@ -88,7 +92,8 @@ def lib():
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
-            if name not in ("lbm_version", "lbm_steps_done", "lbm_free", "lbm_last_error"):
+            if name not in ("lbm_version", "lbm_steps_done", "lbm_free", "lbm_last_error",
+                            "lbm_adjoint_static_scratch_bytes"):
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -420,6 +425,17 @@ class Lbm:
             self._check(lib().lbm_adjoint_step_fields(self._h, state.data_ptr(), fields.data_ptr(), adj_in.data_ptr(),
                                                       adj_out.data_ptr(), ctypes.c_void_p(self._aligned(scratch)),
                                                       grad_theta.data_ptr(), grad_xi.data_ptr()), self._h)
+
+    def adjoint_step_static(self, state, adj_in, adj_out, grad_theta, grad_xi):
+        """adjoint_step with the library's fixed scratch array instead of a caller buffer
+        (lbm_adjoint_step_static: no device allocation in the call)."""
+        if grad_theta.dtype != self.torch.float64 or grad_xi.dtype != self.torch.float64:
+            raise ValueError("gradients accumulate in float64")
+        self._check_adjoint_args(state, adj_in, adj_out)
+        self._need(grad_theta, 8 * self.N, "grad_theta")
+        self._need(grad_xi, 8, "grad_xi")
+        self._check(lib().lbm_adjoint_step_static(self._h, state.data_ptr(), adj_in.data_ptr(), adj_out.data_ptr(),
+                                                  grad_theta.data_ptr(), grad_xi.data_ptr()), self._h)
 
     def set_profiling(self, enable: bool):
         self._check(lib().lbm_set_profiling(self._h, int(bool(enable))), self._h)

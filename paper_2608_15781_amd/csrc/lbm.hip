@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -165,6 +166,7 @@ struct lbm_ctx {
   int nfluid, next;      // list lengths
   int nb_fluid, nb_ext;  // workgroups over each list (multiples of kXcd, 0 if empty)
   bool ordered;          // fluid-list tiles launched in the order stored at L.order
+  void* static_scr;      // device address of the file-scope scratch array on this context's device
   char err[512];
   // Profiling: kEvents events per step of the current chunk (before the first kernel, after each).
   bool prof;
@@ -193,6 +195,40 @@ lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
 
 // Message of the last error of a call without a context (lbm_last_error(NULL)), per thread.
 thread_local char g_err[512] = "";
+
+// Scratch of the allocation-free adjoint step (lbm_adjoint_step_static): a fixed array in the code
+// object, so each device the library runs on holds one copy until the process ends. In host code
+// `scratch` names a host-side stand-in, not device memory: kernels and copies get the device
+// address that hipGetSymbolAddress returns for the current device, resolved once per device by
+// lbm_init (static_scratch below) and kept in the context.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved on the first call for a device), or
+// NULL with `msg` set if it cannot be resolved.
+void* static_scratch(char* msg, size_t len) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    snprintf(msg, len, "hipGetDevice: %s", e != hipSuccess ? hipGetErrorString(e) : "device index out of range");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      snprintf(msg, len, "hipGetSymbolAddress(scratch): %s", e != hipSuccess ? hipGetErrorString(e) : "null address");
+      return nullptr;
+    }
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
+}
 
 lbm_status check_params(const lbm_params* p, char* msg, size_t len) {
   if (!p) { snprintf(msg, len, "params is NULL"); return LBM_ERR_ARG; }
@@ -850,6 +886,10 @@ lbm_status lbm_init(const lbm_params* params, const uint8_t* solid, const double
   c->prof = false;
   for (double& v : c->kernel_ms) v = 0.0;
   c->prof_steps = 0;
+  // The allocation-free adjoint step's scratch on this (the current) device; a failure here only
+  // disables that entry point, which reports it.
+  c->static_scr = static_scratch(c->err, sizeof(c->err));
+  c->err[0] = 0;
   // Stage the host inputs in the second state buffer (free until the first step).
   char* stage = c->ws + L.state[1];
   double* d_theta = reinterpret_cast<double*>(stage);
@@ -1122,6 +1162,28 @@ lbm_status lbm_adjoint_step_fields(lbm_ctx* c, const void* d_state, const void* 
   if (chk != LBM_OK) return chk;
   DISPATCH(c, launch_adj_step, d_state, d_fields, d_adj_in, d_adj_out, d_scratch, d_grad_theta, d_grad_xi);
 }
+
+lbm_status lbm_adjoint_step_static(lbm_ctx* c, const void* d_state, const void* d_adj_in, void* d_adj_out,
+                                   double* d_grad_theta, double* d_grad_xi) {
+  if (!c) return LBM_ERR_ARG;
+  if (!d_state || !d_adj_in || !d_adj_out || !d_grad_theta || !d_grad_xi)
+    return fail(c, LBM_ERR_ARG, "all buffers are required");
+  const size_t need = make_adj_layout(c->p).total;
+  if (need > kStaticScratchBytes)
+    return fail(c, LBM_ERR_ARG, "the adjoint step needs %zu bytes of scratch, more than the %zu of the static "
+                "scratch; use lbm_adjoint_step with a caller-owned scratch buffer", need, kStaticScratchBytes);
+  if (!c->static_scr) {
+    c->static_scr = static_scratch(c->err, sizeof(c->err));
+    if (!c->static_scr) return LBM_ERR_HIP;
+  }
+  void* scr = c->static_scr;
+  const lbm_status chk = check_adjoint_buffers(c, d_state, nullptr, d_adj_in, d_adj_out, scr);
+  if (chk != LBM_OK) return chk;
+  const void* no_fields = nullptr;
+  DISPATCH(c, launch_adj_step, d_state, no_fields, d_adj_in, d_adj_out, scr, d_grad_theta, d_grad_xi);
+}
+
+size_t lbm_adjoint_static_scratch_bytes(void) { return kStaticScratchBytes; }
 
 int64_t lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }
 
