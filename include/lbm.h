@@ -159,7 +159,9 @@ lbm_status lbm_geometry(lbm_ctx* ctx, void* d_info, void* d_wet);
  * (e = -0: pure reactant colour), else e = a. The state holds fluid nodes only: f is the fluid
  * id, the rank of the node among the fluid nodes in node order (0 .. nfluid-1); entries
  * f >= nfluid are unused. In the *_DEV storages a population f is stored as (f - w_i) * 2^k
- * (k = fp16_scale_log2 for FP16, 0 for BF16). Any output pointer may be NULL. */
+ * (k = fp16_scale_log2 for FP16, 0 for BF16); their species part is each node's species total C
+ * (real type, one per fluid id, at g_off plus the 7 planes rounded up to 256 bytes) and the 7
+ * populations as (g_q - w_q C) * 2^k. Any output pointer may be NULL. */
 lbm_status lbm_state_layout(const lbm_params* params, size_t* f_off, size_t* a_off, size_t* g_off,
                             size_t* plane_stride);
 

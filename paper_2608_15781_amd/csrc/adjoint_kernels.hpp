@@ -275,14 +275,14 @@ __global__ __launch_bounds__(kBlock, P == 0 ? 1 : 3) void k_adj_collide(StepArgs
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
         if (i == 1 && outlet) {
-          g[i] = Prec<P>::ld(A.gin[A.ps + t], R(D3Q7::w(1)), A.inv_gscale);
+          g[i] = ld_species(A, 1, t);
         } else {
           const bool bb = (inf >> i) & 1u;
           const int q = bb ? D3Q7::opp[i] : i;
-          g[i] = Prec<P>::ld(A.gin[size_t(q) * A.ps + sid[i]], R(D3Q7::w(i)), A.inv_gscale);
+          g[i] = ld_species(A, q, sid[i]);
         }
       }
-      g[6] = Prec<P>::ld(A.gin[6 * A.ps + t], R(D3Q7::w(6)), A.inv_gscale);
+      g[6] = ld_species(A, 6, t);
       C = 0;
 #pragma unroll
       for (int i = 0; i < 7; ++i) C += g[i];

@@ -40,7 +40,7 @@ size_t real_bytes(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 
 struct Layout {
   size_t info, wet, rhoN, nst, state[2], partials, ring, lists[2], linfo[2], fid, counts, order, total;
-  size_t f_off, a_off, g_off, state_bytes;  // within one state buffer
+  size_t f_off, a_off, g_off, c_off, state_bytes;  // within one state buffer
   size_t ps;  // elements between consecutive state (and adjoint) planes
   int nblocks;  // one thread per node, rounded up to a multiple of kXcd workgroups
 };
@@ -82,7 +82,10 @@ Layout make_layout(const lbm_params& p) {
   L.f_off = 0;
   L.a_off = align_up(19 * s * ps);
   L.g_off = align_up(L.a_off + 4 * r * ps);
-  L.state_bytes = align_up(L.g_off + (p.species ? 7 * s * ps : 0));
+  // 2-byte storages: the species total of each node follows the 7 species planes
+  const bool cplane = p.species && s == 2;
+  L.c_off = align_up(L.g_off + (p.species ? 7 * s * ps : 0));
+  L.state_bytes = align_up(L.c_off + (cplane ? r * ps : 0));
   int nb = int((N + kBlock - 1) / kBlock);
   nb = (nb + kXcd - 1) / kXcd * kXcd;
   L.nblocks = nb;
@@ -358,7 +361,9 @@ __global__ void k_init_state(StepArgs<P> A, const double* rr0, const double* rp0
   st4(A.aout, t, R(pack_frac(rr0[n] / rm, rp0[n] / rm)), R(0), R(0), R(0));
   if (A.species) {
     const double c = c0 ? c0[n] : 1.0;
-    for (int i = 0; i < 7; ++i) A.gout[size_t(i) * A.ps + t] = Prec<P>::st(R(D3Q7::w(i) * c), R(D3Q7::w(i)), A.gscale);
+    if (P >= 2) A.cout[t] = R(c);  // deviations from w_q C: zero at rest
+    for (int i = 0; i < 7; ++i)
+      A.gout[size_t(i) * A.ps + t] = Prec<P>::st(R(D3Q7::w(i) * c), P >= 2 ? R(D3Q7::w(i)) * R(c) : R(D3Q7::w(i)), A.gscale);
   }
 }
 
@@ -467,9 +472,11 @@ StepArgs<P> make_args(lbm_ctx* c, int src_buf) {
   A.fin = reinterpret_cast<const S*>(sb + L.f_off);
   A.ain = reinterpret_cast<const R*>(sb + L.a_off);
   A.gin = reinterpret_cast<const S*>(sb + L.g_off);
+  A.cin = reinterpret_cast<const R*>(sb + L.c_off);
   A.fout = reinterpret_cast<S*>(db + L.f_off);
   A.aout = reinterpret_cast<R*>(db + L.a_off);
   A.gout = reinterpret_cast<S*>(db + L.g_off);
+  A.cout = reinterpret_cast<R*>(db + L.c_off);
   A.rhoN = reinterpret_cast<R*>(c->ws + L.rhoN);
   A.nst = reinterpret_cast<R*>(c->ws + L.nst);
   A.wet = reinterpret_cast<const R*>(c->ws + L.wet);
@@ -552,9 +559,11 @@ lbm_status launch_step_from(lbm_ctx* c, const void* src, void* dst, void* fields
   A.fin = reinterpret_cast<const S*>(sb + c->L.f_off);
   A.ain = reinterpret_cast<const R*>(sb + c->L.a_off);
   A.gin = reinterpret_cast<const S*>(sb + c->L.g_off);
+  A.cin = reinterpret_cast<const R*>(sb + c->L.c_off);
   A.fout = db ? reinterpret_cast<S*>(db + c->L.f_off) : nullptr;
   A.aout = db ? reinterpret_cast<R*>(db + c->L.a_off) : nullptr;
   A.gout = db ? reinterpret_cast<S*>(db + c->L.g_off) : nullptr;
+  A.cout = db ? reinterpret_cast<R*>(db + c->L.c_off) : nullptr;
   if (fields) use_fields<P>(c, A, fields);
   A.ring_row = reinterpret_cast<double*>(c->ws + c->L.ring);
   A.red_out = nullptr;
@@ -701,9 +710,11 @@ StepArgs<P> make_args_from(lbm_ctx* c, const void* state) {
   A.fin = reinterpret_cast<const S*>(sb + c->L.f_off);
   A.ain = reinterpret_cast<const R*>(sb + c->L.a_off);
   A.gin = reinterpret_cast<const S*>(sb + c->L.g_off);
+  A.cin = reinterpret_cast<const R*>(sb + c->L.c_off);
   A.fout = nullptr;
   A.aout = nullptr;
   A.gout = nullptr;
+  A.cout = nullptr;
   return A;
 }
 

@@ -253,9 +253,11 @@ struct StepArgs {
   const S* fin;  // 19 planes f^m
   const R* ain;  // per node 4-vector (e, vx, vy, vz), e = pack_frac(a, b)
   const S* gin;  // 7 planes species
+  const R* cin;  // 2-byte storages: the species total of each node (deviation reference of gin)
   S* fout;
   R* aout;
   S* gout;
+  R* cout;
   R* rhoN;       // 1 plane, rho^N in the form of rn_value
   R* rm_out;     // optional: rho^m of each fluid node (adjoint recompute)
   R* nst;        // per fluid id 4-vector (n*_x, n*_y, n*_z, |grad rho^N|)
@@ -283,6 +285,19 @@ struct StepArgs {
   R* m_u;
   R* m_c;
 };
+
+// Species storage. FP32 and FP64 hold the populations g_q themselves. The 2-byte storages hold
+// each node's post-collision species total C (arithmetic type, plane cin/cout) and the
+// populations as deviations (g_q - w_q C) 2^k from the equilibrium at rest of that total: those
+// are small (advection and non-equilibrium parts only) wherever C lies in [0, 1], so the 11 or 8
+// significant bits of the storage apply to them and not to C itself. Population q of the node with
+// fluid id src:
+template <int P>
+__device__ inline typename Prec<P>::R ld_species(const StepArgs<P>& A, int q, int src) {
+  using R = typename Prec<P>::R;
+  const R w = R(D3Q7::w(q));
+  return Prec<P>::ld(A.gin[size_t(q) * A.ps + src], P >= 2 ? w * A.cin[src] : w, A.inv_gscale);
+}
 
 // Sum of the per-workgroup partials (5 planes of nparts) by one workgroup of kBlock threads, in
 // a fixed order: strided per-thread sums, then wavefront shuffles, then the waves in order. Every
@@ -583,9 +598,9 @@ __device__ inline void pull_node(const StepArgs<P>& A, int t, uint32_t inf, cons
       const bool bb = !own && ((inf >> i) & 1u);
       const int src = own ? t : sid[i];
       const int q = own ? 1 : (bb ? D3Q7::opp[i] : i);
-      g[i] = Prec<P>::ld(A.gin[size_t(q) * A.ps + src], R(D3Q7::w(i)), A.inv_gscale);
+      g[i] = ld_species(A, q, src);
     }
-    g[6] = Prec<P>::ld(A.gin[6 * A.ps + t], R(D3Q7::w(6)), A.inv_gscale);
+    g[6] = ld_species(A, 6, t);
   }
 }
 
@@ -742,15 +757,19 @@ __device__ inline void collide_node(const StepArgs<P>& A, int t, int n, uint32_t
       const bool inlet = inf & kInlet;
       const R sink = (delta != R(0)) ? R(1) - delta / C : R(1);
       const R cu[7] = {upx, -upx, upy, -upy, upz, -upz, R(0)};
+      R go[7];
       R gs = 0;
 #pragma unroll
       for (int i = 0; i < 7; ++i) {
         const R geq = R(D3Q7::w(i)) * C * (R(1) + R(4) * cu[i]);
         const R gi = inlet ? geq : g[i];
-        const R go = (gi + (geq - gi) * A.inv_tau_c) * sink;
-        gs += go;
-        A.gout[size_t(i) * A.ps + t] = Prec<P>::st(go, R(D3Q7::w(i)), A.gscale);
+        go[i] = (gi + (geq - gi) * A.inv_tau_c) * sink;
+        gs += go[i];
       }
+      if (P >= 2) A.cout[t] = gs;  // the deviation reference of the stored populations
+#pragma unroll
+      for (int i = 0; i < 7; ++i)
+        A.gout[size_t(i) * A.ps + t] = Prec<P>::st(go[i], P >= 2 ? R(D3Q7::w(i)) * gs : R(D3Q7::w(i)), A.gscale);
       ok = ok && finite(gs);
     }
     red5[0] += double(rr);
@@ -821,7 +840,7 @@ __global__ __launch_bounds__(kBlock) void k_state_sums(StepArgs<P> A) {
     R C = 0;
     if (A.species)
 #pragma unroll
-      for (int i = 0; i < 7; ++i) C += Prec<P>::ld(A.gin[size_t(i) * A.ps + t], R(D3Q7::w(i)), A.inv_gscale);
+      for (int i = 0; i < 7; ++i) C += ld_species(A, i, t);
     red5[0] = double(a) * double(s);
     red5[1] = double(b) * double(s);
     red5[3] = double(C);
@@ -859,7 +878,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(StepArgs<P> A, typename Prec<
   if (go) {
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-      go[size_t(i) * N + n] = (fluid && A.species) ? Prec<P>::ld(A.gin[size_t(i) * A.ps + fi], R(D3Q7::w(i)), A.inv_gscale) : R(0);
+      go[size_t(i) * N + n] = (fluid && A.species) ? ld_species(A, i, fi) : R(0);
   }
 }
 

@@ -44,10 +44,11 @@ def test_workspace_sizes_scale_with_precision(core):
         assert core.lib().lbm_state_bytes(ctypes.byref(p), ctypes.byref(s)) == 0
         sizes[prec] = (b.value, s.value)
     N = 64 ** 3
-    # state = 19 populations + 4 scalars + 7 species populations per node
+    # state = 19 populations + 4 scalars + 7 species populations per node (+ the species total in
+    # the arithmetic type with 2-byte storage)
     assert sizes["fp64"][1] >= (19 + 4 + 7) * 8 * N
     assert sizes["fp32"][1] >= (19 + 4 + 7) * 4 * N
-    assert sizes["fp16"][1] >= (19 + 7) * 2 * N + 4 * 4 * N
+    assert sizes["fp16"][1] >= (19 + 7) * 2 * N + (4 + 1) * 4 * N
     assert sizes["fp16"][1] < sizes["fp32"][1] < sizes["fp64"][1]
 
 
@@ -66,7 +67,8 @@ def test_state_layout_and_plane_stride(core, prec, s, r, species):
     assert f.value == 0 and a.value >= 19 * s * ps.value and g.value >= a.value + 4 * r * ps.value
     sb = ctypes.c_size_t()
     assert core.lib().lbm_state_bytes(ctypes.byref(p), ctypes.byref(sb)) == 0
-    assert sb.value >= g.value + (7 * s * ps.value if species else 0)
+    cplane = r * ps.value if (species and s == 2) else 0  # species totals after the 2-byte planes
+    assert sb.value >= g.value + (7 * s * ps.value if species else 0) + cplane
     ab, scr = ctypes.c_size_t(), ctypes.c_size_t()
     assert core.lib().lbm_adjoint_bytes(ctypes.byref(p), ctypes.byref(ab), ctypes.byref(scr)) == 0
     assert ab.value >= 30 * r * ps.value
