@@ -8,7 +8,8 @@ function per step of the paper's Sec. II and Appendix A); this module only marsh
 Parity status: every function is pinned by CPU tests against closed forms, invariants or
 library routines (lattice isotropy, equilibrium moments, a numerical solve of the central-moment
 transform, the Akai construction, Poiseuille flow, shear-wave decay, the Laplace law, the
-contact angle on a flat wall, D3Q7 species decay, the species inlet and outflow planes against
+contact angle on a flat wall (60, 90 and 120 deg from a semicircle; 15, 30 and 150 deg from caps started
+10 to 25 deg away; the same angles with the realignment cone narrowed or removed), D3Q7 species decay, the species inlet and outflow planes against
 the diffusion series, mass and conversion bookkeeping, symmetry).
 """
 from __future__ import annotations

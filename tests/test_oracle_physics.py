@@ -102,6 +102,101 @@ def test_contact_angle_flat_wall(oracle_mod, theta_deg):
     assert abs(th - theta_deg) < 5.0, th
 
 
+def _segment_cap(nx, nz, area, theta_deg):
+    """Red circular segment of the given area whose arc meets the wall z = 0.5 at theta_deg
+    (through red), centred in x; walls at z = 0 and z = nz - 2, nz - 1 (three nodes thick with
+    the periodic image)."""
+    th = np.radians(theta_deg)
+    R = np.sqrt(area / (th - np.sin(th) * np.cos(th)))
+    zc = 0.5 - R * np.cos(th)
+    z, x = np.meshgrid(np.arange(nz), np.arange(nx), indexing="ij")
+    red = (np.sqrt((x - nx / 2 + 0.5) ** 2 + (z - zc) ** 2) < R) & (z >= 1) & (z <= nz - 3)
+    solid = np.zeros((nz, 1, nx), np.uint8)
+    solid[0] = solid[nz - 1] = solid[nz - 2] = 1
+    return solid, red.astype(float)[:, None, :]
+
+
+def _circle_angle(rn, zmin):
+    """Contact angle through red of a cap on the wall z = 0.5: circle fit (algebraic least squares)
+    to the rho^N = 0 crossings along rows and columns at z >= zmin, then cos(theta) = -(z_c - 0.5)/R."""
+    nz, nx = rn.shape
+    xs, zs = [], []
+    for x in range(nx):
+        for z in range(1, nz - 3):
+            a, b = rn[z, x], rn[z + 1, x]
+            if (a > 0) != (b > 0) and z + a / (a - b) >= zmin:
+                xs.append(x); zs.append(z + a / (a - b))
+    for z in range(int(np.ceil(zmin)), nz - 2):
+        for x in range(nx):
+            a, b = rn[z, x], rn[z, (x + 1) % nx]
+            if (a > 0) != (b > 0):
+                xs.append(x + a / (a - b)); zs.append(z)
+    x, z = np.array(xs, float), np.array(zs, float)
+    sol = np.linalg.lstsq(np.stack([x, z, np.ones_like(x)], 1), x * x + z * z, rcond=None)[0]
+    xc, zc = sol[0] / 2, sol[1] / 2
+    R = np.sqrt(sol[2] + xc * xc + zc * zc)
+    return float(np.degrees(np.arccos(np.clip(-(zc - 0.5) / R, -1.0, 1.0))))
+
+
+# Caps at the sweep's extreme angles. Started 10 to 25 degrees away from the imposed angle, each
+# must move toward it and end within 5 degrees. The low-angle caps are wide and flat (large x
+# extent, apex height 11-15 nodes); tau = 0.6 and sigma = 0.06 make the contact lines relax within
+# a few thousand steps (with tau = 1, sigma = 0.01 a 15 degree cap still spreads after 10^4 steps).
+# Measured: 15 deg from 25 -> 17.9 after 8000 steps (15.7 when started at 15), 30 from 50 -> 30.6,
+# 150 from 125 -> 152.2. The deviation of the static angle is first order in 1/R (at tau = 1,
+# sigma = 0.01, 150 deg: 12.6 deg at R = 10, 5.6 at R = 20, 3.7 at R = 30).
+EXTREME_CAPS = {15.0: dict(nx=240, nz=42, area=1200.0, start=25.0, steps=8000, zmin=2.0),
+                30.0: dict(nx=200, nz=42, area=1200.0, start=50.0, steps=4000, zmin=3.5),
+                150.0: dict(nx=100, nz=42, area=308.0, start=125.0, steps=4000, zmin=3.5)}
+
+
+@pytest.mark.parametrize("theta_deg", sorted(EXTREME_CAPS))
+def test_contact_angle_extreme_angles(oracle_mod, theta_deg):
+    """Akai wetting (eq. realigned_normal_vectors) at the sweep's extreme contact angles: a quasi-2D
+    red cap started away from the imposed angle relaxes to within 5 degrees of it, measured
+    through red by a circle fit of the interface away from the wall."""
+    c = EXTREME_CAPS[theta_deg]
+    solid, red = _segment_cap(c["nx"], c["nz"], c["area"], c["start"])
+    o = oracle_mod.Oracle((c["nx"], 1, c["nz"]), solid=solid, theta=np.deg2rad(theta_deg), rho_r0=red,
+                          rho_p0=(1 - solid) - red, tau=0.6, sigma=0.06, beta=0.7)
+    th0 = _circle_angle(o.moments()["rho_n"][:, 0, :], c["zmin"])
+    o.step(c["steps"])
+    th = _circle_angle(o.moments()["rho_n"][:, 0, :], c["zmin"])
+    print("cap %g deg: started at %.2f, %.2f after %d steps" % (theta_deg, th0, th, c["steps"]))
+    assert abs(th - theta_deg) < 5.0, th
+    assert abs(th0 - theta_deg) - abs(th - theta_deg) > 5.0, (th0, th)  # it moved toward the angle
+
+
+def test_akai_cone_does_not_set_the_contact_angle(oracle_mod):
+    """The realignment keeps n inside a cone sin(theta') < 1e-2 around +-n_s (the rotation plane is
+    undefined there). That cone is a guard against rounding, not part of the wetting physics: caps at
+    15 deg (the interface nearest to parallel with the wall) and at 150 deg give the same contact
+    angle, to 0.01 deg, with the cone, with a cone ten times narrower and with none, and the colour
+    fields differ by less than 1e-5 (measured: 1.2e-6 and 4e-9 at 15 deg, where a few nodes enter
+    the cone for a while; bitwise equal at 150 deg). So the angles pinned above do not depend on
+    the cone's size."""
+    runs = [(15.0, dict(nx=240, nz=42, area=1200.0, start=15.0, steps=1500, zmin=2.0)),
+            (150.0, dict(nx=100, nz=42, area=308.0, start=125.0, steps=1500, zmin=3.5))]
+    try:
+        for theta_deg, c in runs:
+            solid, red = _segment_cap(c["nx"], c["nz"], c["area"], c["start"])
+            out = []
+            for cone in (1e-2, 1e-3, 0.0):
+                oracle_mod.set_akai_cone(cone)
+                o = oracle_mod.Oracle((c["nx"], 1, c["nz"]), solid=solid, theta=np.deg2rad(theta_deg), rho_r0=red,
+                                      rho_p0=(1 - solid) - red, tau=0.6, sigma=0.06, beta=0.7)
+                o.step(c["steps"])
+                rn = o.moments()["rho_n"]
+                out.append((rn, _circle_angle(rn[:, 0, :], c["zmin"])))
+            for rn, th in out[1:]:
+                print("cone check %g deg: angle %.4f vs %.4f, max |d rho^N| %.2e" % (
+                    theta_deg, th, out[0][1], np.abs(rn - out[0][0]).max()))
+                assert abs(th - out[0][1]) < 0.01
+                assert np.abs(rn - out[0][0]).max() < 1e-5
+    finally:
+        oracle_mod.set_akai_cone(1e-2)
+
+
 def test_species_decay_matches_fourier_evolution(oracle_mod):
     """D3Q7 species at rest (u = 0): C = 1 + A sin(kx) evolves exactly by the 7x7 one-step
     Fourier matrix of pull + BGK, and decays like exp(-D k^2 t), D = (tau_C - 1/2)/4."""
