@@ -147,8 +147,8 @@ def report(args):
     wr = summarize(args.write, copy_bytes)["counters"]["WRITE_SIZE"]
     fluid = args.fluid_nodes
     adj = args.mode == "adjoint"
-    drv = "python3 -m paper_2608_15781_amd.profile_run %s--precision %s --steps " % ("adjoint " if adj else "",
-                                                                                    args.precision)
+    drv = "python3 -m paper_2608_15781_amd.profile_run %s--precision %s --steps " % (
+        "adjoint " if adj else "--workload %s " % args.workload, args.precision)
     steps = (200, 40) if adj else (50, 20)
     title = ("Adjoint kernels, adjoint96 (forward with checkpoints every 20 steps, then the checkpointed backward)"
              if adj else "Step kernels, %s" % args.workload)
@@ -159,7 +159,8 @@ def report(args):
              "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o run -- %s%d" % (drv, steps[1]),
              "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o run -- %s%d" % (drv, steps[1]),
              "python3 -m paper_2608_15781_amd.profile_run report %s--precision %s --fluid-nodes %d "
-             "OUT/prof OUT/fetch OUT/write" % ("--mode adjoint " if adj else "", args.precision, fluid),
+             "OUT/prof OUT/fetch OUT/write" % ("--mode adjoint " if adj else "--workload %s " % args.workload,
+                                               args.precision, fluid),
              "```", "",
              "Counter calibration: the run ends with a %d MiB device copy (source evicted from the last-level "
              "cache first); it reads FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB for %.0f KiB moved each way, "
@@ -199,18 +200,19 @@ def report(args):
     print("\n".join(lines))
 
 
-BENCH_ARGS = "--steps 200 --warmup 20 --no-cpu --no-adjoint --modes \"\""
+BENCH_ARGS = "--steps 20 --warmup 5 --no-cpu --no-adjoint --no-side"
+STEP_KERNELS = ("lbm::k_colour<%d>", "lbm::k_extrap<%d>", "lbm::k_normal<%d>", "lbm::k_collide<%d, false>")
 
 
 def bench_trace(args):
     """Markdown summary of a kernel trace of bench.py itself (args.out: the trace folder,
-    args.fetch: the JSON line that run printed), beside the bench's own event timing of the
-    collide kernel from the same run."""
+    args.fetch: the JSON line that run printed): the average duration of each step kernel of the
+    FP32 headline's profiled pass beside the bench's own event timing of the same kernels."""
     kt = summarize(args.out, 0)["kernels"]
     with open(args.fetch) as f:
         bench = json.loads(f.read().strip().splitlines()[-1])
     roof = bench["roofline"]
-    lines = ["# bench.py under the kernel tracer, 128^3 workload, fp32 headline (with its fp64 reference run)", "",
+    lines = ["# bench.py under the kernel tracer: the 512^3 headline workload, FP32 and FP16 storage", "",
              "Command (repository root, `cd /tmp && export TMPDIR=/tmp` first, `PYTHONPATH` = repository root):", "",
              "```",
              "rocprofv3 --kernel-trace --stats --output-format csv -d OUT/prof -o run -- python3 bench.py %s "
@@ -222,23 +224,26 @@ def bench_trace(args):
         if name.startswith("lbm::"):
             lines.append("| `%s` | %d | %.2f | %.2f | %.2f |" % (name, k["calls"], k["avg_us"], k["min_us"],
                                                                 k["max_us"]))
-    # the launches bench.py timed with events: its FP32 profiled pass, the last `steps` FP32
-    # collide launches of the run (the FP64 reference run uses other kernels)
+    # the FP32 headline's profiled pass: the last `steps` launches of each FP32 step kernel before the
+    # FP16 run starts (every FP32 launch of the run comes first)
     trace = sorted(_rows(os.path.join(args.out, "**", "*kernel_trace.csv")), key=lambda r: int(r["Start_Timestamp"]))
-    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace
-           if _short(r["Kernel_Name"]) == "lbm::k_collide<1, false>"]
-    timed = dur[-bench["steps"]:]
-    lines += ["", "Same run, bench.py's own figures: %.1f MFLUPS over %d timed steps; collide kernel %.2f us per "
-              "launch from HIP events on the library's stream over its profiled pass of %d steps, whose %d "
-              "launches the tracer measures at %.2f us on average (all %d FP32 collide launches of the run: "
-              "%.2f us); roofline achieved %.1f GB/s = %.3f of %.0f GB/s. Under the tracer each event bracket "
-              "also holds the tracer's own per-dispatch work, so the event figure reads %.1f%% above the "
-              "kernel-only one here; without the tracer the bench's event figure and a separate kernel trace of "
-              "the same workload agree to about 2%% (the step-kernel summaries)." % (
-                  bench["value"], bench["steps"], 1e3 * roof["avg_launch_ms"], bench["steps"], len(timed),
-                  sum(timed) / max(1, len(timed)), len(dur), sum(dur) / max(1, len(dur)), roof["achieved"],
-                  roof["frac"], roof["peak"],
-                  100.0 * (1e3 * roof["avg_launch_ms"] / (sum(timed) / max(1, len(timed))) - 1.0)), ""]
+    rows = ["", "| kernel (FP32 headline, profiled pass) | tracer avg us | bench.py event avg us |", "|---|---|---|"]
+    tracer_sum = 0.0
+    for name, key in zip(STEP_KERNELS, ("colour", "extrap", "normal", "collide")):
+        kname = name % 1
+        dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace
+               if _short(r["Kernel_Name"]) == kname]
+        timed = dur[-bench["steps"]:]
+        avg = sum(timed) / max(1, len(timed))
+        tracer_sum += avg
+        rows.append("| `%s` | %.2f | %.2f |" % (kname, avg, 1e3 * roof["kernel_ms"].get(key, 0.0)))
+    lines += rows
+    lines += ["", "Same run, bench.py's own figures: %.1f MFLUPS over %d timed steps; step %.2f us from HIP events "
+              "on the library's stream (tracer: %.2f us, the sum of the four kernels' averages over the same "
+              "launches); roofline achieved %.1f GB/s = %.4f of %.0f GB/s at %d algorithmic bytes per fluid "
+              "update. Under the tracer each event bracket also holds the tracer's own per-dispatch work." % (
+                  bench["value"], bench["steps"], 1e3 * roof["avg_step_ms"], tracer_sum, roof["achieved"],
+                  roof["frac"], roof["peak"], roof["alg_bytes_per_fluid_update"]), ""]
     print("\n".join(lines))
 
 
@@ -283,10 +288,10 @@ def counters(args):
              "```"]
     for k, ctrs in enumerate(COUNTER_PASSES):
         lines.append("rocprofv3 --pmc %s --output-format csv -d OUT/pass%s -o run -- python3 -m "
-                     "paper_2608_15781_amd.profile_run --precision %s --steps %d"
-                     % (ctrs, "AB"[k], args.precision, args.steps))
-    lines += ["python3 -m paper_2608_15781_amd.profile_run counters --precision %s OUT/passA OUT/passB"
-              % args.precision, "```", "",
+                     "paper_2608_15781_amd.profile_run --workload %s --precision %s --steps %d"
+                     % (ctrs, "AB"[k], args.workload, args.precision, args.steps))
+    lines += ["python3 -m paper_2608_15781_amd.profile_run counters --workload %s --precision %s --steps %d "
+              "OUT/passA OUT/passB" % (args.workload, args.precision, args.steps), "```", "",
               "| kernel | dispatches | us (counter run) | TA busy | TA stalled on L2 | L2 hit | VMEM reads per wave |",
               "|---|---|---|---|---|---|---|"]
 
