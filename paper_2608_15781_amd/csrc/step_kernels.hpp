@@ -233,6 +233,75 @@ __device__ inline void pull_sources_lean(const int* fid, const Nbr& nb, int t, u
   }
 }
 
+// Cross-lane moves within the 64-wide wave (DPP wave shifts, one VALU move per 32-bit word): the
+// value that lane l - 1 (from_below) or lane l + 1 (from_above) holds in the same register. The end
+// lanes of the wave receive their own value; callers use the result only where the neighbouring
+// lane is active and holds the wanted node.
+__device__ inline int lane_from_below(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ inline int lane_from_above(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+template <int DIR>
+__device__ inline float lane_move(float v) {
+  const int b = __float_as_int(v);
+  return __int_as_float(DIR < 0 ? lane_from_below(b) : lane_from_above(b));
+}
+template <int DIR>
+__device__ inline double lane_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = int(uint32_t(b)), hi = int(uint32_t(uint64_t(b) >> 32));
+  const int mlo = DIR < 0 ? lane_from_below(lo) : lane_from_above(lo);
+  const int mhi = DIR < 0 ? lane_from_below(hi) : lane_from_above(hi);
+  return __longlong_as_double((long long)((uint64_t(uint32_t(mhi)) << 32) | uint32_t(mlo)));
+}
+template <int DIR>
+__device__ inline float4 lane_move(const float4& v) {
+  return make_float4(lane_move<DIR>(v.x), lane_move<DIR>(v.y), lane_move<DIR>(v.z), lane_move<DIR>(v.w));
+}
+template <int DIR>
+__device__ inline double4 lane_move(const double4& v) {
+  return make_double4(lane_move<DIR>(v.x), lane_move<DIR>(v.y), lane_move<DIR>(v.z), lane_move<DIR>(v.w));
+}
+
+// Values of a per-node quantity at the 18 neighbours x - c_i of fluid node x (out[i]), fetched with
+// one gather per row. The sources x - c_i with c_ix != 0 lie on the row of the source
+// x - (0, c_iy, c_iz) of the partner direction, one node along x; when the node's own neighbour
+// x - c_ix along the row is fluid, it is the next fluid id and lane l - c_ix of the same wave holds
+// it, and that lane's partner value is exactly the one wanted. Those values are moved across lanes
+// instead of gathered, so each row triple costs one gather; the other lanes (wave ends, periodic
+// wrap, a solid neighbour along x) gather their own. ld(i) gathers the value of direction i; own is
+// the node's own value (the source of the x-shifted directions of the node's own row). SOLID_OWN:
+// where x - c_i is solid the node's own value stands in (state vectors, whose solid sources are
+// bounce-back); otherwise every neighbour has a value of its own (rho^N, extrapolated into solids).
+// Every 64 consecutive threads of a launch hold consecutive fluid ids.
+template <bool SOLID_OWN, class T, class Load>
+__device__ inline void row_shared(const Nbr& nb, uint32_t inf, const T& own, Load ld, T out[18]) {
+  using D = D3Q19;
+  const int lane = __lane_id();
+  // lane l - 1 holds node x - 1 of this row (direction 0 pulls from x - 1), lane l + 1 node x + 1
+  const bool below = !(inf & 1u) && nb.dxm == -1 && lane > 0;
+  const bool above = !((inf >> 1) & 1u) && nb.dxp == 1 && lane < 63;
+  // The gathers: partner directions (c_ix = 0) for every lane, x-shifted directions only where the
+  // neighbouring lane cannot supply them, all issued before any cross-lane move.
+  T gathered[18];
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    const bool solid = SOLID_OWN && ((inf >> i) & 1u);
+    if (D::cx[i] == 0) {
+      out[i] = ld(i);
+    } else if (!solid && !(D::cx[i] > 0 ? below : above)) {
+      gathered[i] = ld(i);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    if (D::cx[i] == 0) continue;
+    const int m = yz_partner(i);
+    const T base = (m < 0) ? own : out[m];
+    const T moved = (D::cx[i] > 0) ? lane_move<-1>(base) : lane_move<+1>(base);
+    const bool solid = SOLID_OWN && ((inf >> i) & 1u);
+    out[i] = solid ? own : ((D::cx[i] > 0 ? below : above) ? moved : gathered[i]);
+  }
+}
+
 template <int P>
 struct StepArgs {
   using S = typename Prec<P>::S;
@@ -360,6 +429,9 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
   const Nbr nb = make_nbr(n, A.geo);
   int sid[18];
   pull_sources(A.fid, nb, t, inf, sid);
+  const typename V4<R>::T own = ld4(A.ain, t);
+  typename V4<R>::T avs[18];  // (e, v) at the sources (own where solid: bounce-back)
+  row_shared<true>(nb, inf, own, [&](int i) { return ld4(A.ain, sid[i]); }, avs);
   R rm = 0, rr = 0, rp = 0;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
@@ -368,8 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
     const int q = bb ? D::opp[i] : i;
     const R sgn = bb ? R(-1) : R(1);  // c_q = sgn * c_i
     const R fm = Prec<P>::ld(A.fin[size_t(q) * A.ps + src], R(D::w(i)), A.inv_scale);
-    const typename V4<R>::T av = ld4(A.ain, src);
-    // all three products, zeros included, so that the 4-vector is fetched by one wide load
+    const typename V4<R>::T av = (i == 18) ? own : avs[i];
     const R cv = R(D::cx[i]) * av.y + R(D::cy[i]) * av.z + R(D::cz[i]) * av.w;
     R a, b;
     unpack_frac(av.x, a, b);
@@ -488,11 +559,13 @@ __global__ __launch_bounds__(kBlock) void k_normal(StepArgs<P> A) {
   typename V4<R>::T wv;
   wv.x = wv.y = wv.z = wv.w = R(0);
   if (inf & kWet) wv = ld4(A.wet, t);
+  R src[18];  // rho^N at x - c_i (solid neighbours hold their extrapolated colour)
+  row_shared<false>(nb, inf, A.rhoN[n], [&](int i) { return A.rhoN[nb.at(-D::cx[i], -D::cy[i], -D::cz[i])]; }, src);
   R d[9];
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     const int p = D::half[j];
-    d[j] = rn_diff(A.rhoN[nb.at(D::cx[p], D::cy[p], D::cz[p])], A.rhoN[nb.at(-D::cx[p], -D::cy[p], -D::cz[p])]);
+    d[j] = rn_diff(src[D::opp[p]], src[p]);  // x + c_p is the source of opp(p)
   }
   R nv[3], len, raw[3];
   bool raw_set;
@@ -807,11 +880,10 @@ __global__ __launch_bounds__(kBlock) void k_collide(StepArgs<P> A) {
     // opp(i), the node's own id where it is solid, which is the value the curvature takes for a
     // solid neighbour.
     const typename V4<R>::T nsv = ld4(A.nst, t);
-    typename V4<R>::T nbv[18];
-#pragma unroll
-    for (int i = 0; i < 18; ++i) nbv[i] = ld4(A.nst, sid[D::opp[i]]);
+    typename V4<R>::T srcv[18];
+    row_shared<true>(nb, inf, nsv, [&](int i) { return ld4(A.nst, sid[i]); }, srcv);
     typename V4<R>::T cur = nsv;
-    cur.w = curvature_hg<R>(nsv, A.eps, [&](int i) { return nbv[i]; });
+    cur.w = curvature_hg<R>(nsv, A.eps, [&](int i) { return srcv[D::opp[i]]; });
     collide_node<P, MOM>(A, t, n, inf, f, g, rn, cur, red5);
   }
   if (!MOM) block_reduce5(red5, A.partials);
