@@ -625,14 +625,31 @@ __device__ inline typename Prec<P>::R grad_transpose(const StepArgs<P>& A, const
   // Every load is issued before any is used; a direction whose source is solid reads this
   // node's own entries and is discarded.
   R gx[18], gy[18], gz[18];
+  if (EXT) {
 #pragma unroll
-  for (int i = 0; i < 18; ++i) {
-    // fluid y: bit i set means y - c_i is solid; solid y: bit opp(i) set means y - c_i is fluid
-    const bool src_fluid = EXT ? ((inf >> D::opp[i]) & 1u) : !((inf >> i) & 1u);
-    const int m = src_fluid ? nb.at(-D::cx[i], -D::cy[i], -D::cz[i]) : n;
-    gx[i] = D::cx[i] ? J.lG[m] : R(0);
-    gy[i] = D::cy[i] ? J.lG[N + m] : R(0);
-    gz[i] = D::cz[i] ? J.lG[2 * N + m] : R(0);
+    for (int i = 0; i < 18; ++i) {
+      // solid y: bit opp(i) set means y - c_i is fluid
+      const bool src_fluid = (inf >> D::opp[i]) & 1u;
+      const int m = src_fluid ? nb.at(-D::cx[i], -D::cy[i], -D::cz[i]) : n;
+      gx[i] = D::cx[i] ? J.lG[m] : R(0);
+      gy[i] = D::cy[i] ? J.lG[N + m] : R(0);
+      gz[i] = D::cz[i] ? J.lG[2 * N + m] : R(0);
+    }
+  } else {
+    // Fluid y (bit i set: y - c_i is solid, read as y and discarded): each component plane with
+    // one gather per row triple. A component is read where c_i has it, and at the row centres
+    // whose x-neighbours need it.
+    auto plane = [&](const R* g, int a, R out[18]) {
+      row_shared<true>(nb, inf, g[n], [&](int i) {
+        const int c = a == 0 ? D::cx[i] : (a == 1 ? D::cy[i] : D::cz[i]);
+        const bool centre = D::cx[i] == 0 && (D::cy[i] == 0 || D::cz[i] == 0);
+        const bool need = c != 0 || (a == 0 && centre);
+        return need ? g[((inf >> i) & 1u) ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i])] : R(0);
+      }, out);
+    };
+    plane(J.lG, 0, gx);
+    plane(J.lG + N, 1, gy);
+    plane(J.lG + 2 * N, 2, gz);
   }
   R s = 0;
 #pragma unroll
@@ -713,11 +730,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_final(StepArgs<P> A, AdjArgs<typ
   R a, b;
   unpack_frac(ld4(A.ain, t).x, a, b);
   R la = 0, lv[3] = {0, 0, 0};
+  // The readers' pairs: y + c_q is the neighbour y - c_opp(q); where it is solid the reader is y
+  // itself (bounce-back), and y for the rest population.
+  using V2R = typename V2<R>::T;
+  const V2R* lr2 = reinterpret_cast<const V2R*>(J.lr2);
+  const V2R own2 = lr2[n];
+  V2R rdv[18];
+  row_shared<true>(nb, inf, own2,
+                   [&](int i) { return lr2[((inf >> i) & 1u) ? n : nb.at(-D::cx[i], -D::cy[i], -D::cz[i])]; }, rdv);
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
-    const bool self = (q == 18) || ((inf >> D::opp[q]) & 1u);  // y + c_q solid: bounce-back reader
-    const int rd = self ? n : nb.at(D::cx[q], D::cy[q], D::cz[q]);
-    const typename V2<R>::T lv2 = reinterpret_cast<const typename V2<R>::T*>(J.lr2)[rd];
+    const V2R lv2 = (q == 18) ? own2 : rdv[D::opp[q]];
     const R lr = lv2.x, lm = lv2.y;
     const R fq = Prec<P>::ld(A.fin[size_t(q) * A.ps + t], R(D::w(q)), A.inv_scale);
     J.lout[size_t(q) * A.ps + t] += lr * a + lm;

@@ -253,6 +253,14 @@ __device__ inline double lane_move(double v) {
   return __longlong_as_double((long long)((uint64_t(uint32_t(mhi)) << 32) | uint32_t(mlo)));
 }
 template <int DIR>
+__device__ inline float2 lane_move(const float2& v) {
+  return make_float2(lane_move<DIR>(v.x), lane_move<DIR>(v.y));
+}
+template <int DIR>
+__device__ inline double2 lane_move(const double2& v) {
+  return make_double2(lane_move<DIR>(v.x), lane_move<DIR>(v.y));
+}
+template <int DIR>
 __device__ inline float4 lane_move(const float4& v) {
   return make_float4(lane_move<DIR>(v.x), lane_move<DIR>(v.y), lane_move<DIR>(v.z), lane_move<DIR>(v.w));
 }

@@ -17,9 +17,13 @@ FP64_TOL = 1e-10
 FP32_TOL = 2e-4
 HALF_TOL = 2e-2
 BF16_TOL = 1e-1
-# FP32 on the 48^3 crop of the benchmark mask after 2000 steps (see that test)
+# FP32, FP16 and BF16 storage on the 48^3 crop of the benchmark mask after 2000 steps (see that test)
 CROP_FP32_TOL = 3e-3
 CROP_FP32_U_L2 = 2e-3
+CROP_FP16_TOL = 3e-3
+CROP_FP16_U_L2 = 2e-3
+CROP_BF16_TOL = 1e-2
+CROP_BF16_U_L2 = 8e-3
 
 
 def _rel(a, b):
@@ -489,8 +493,13 @@ def test_bench_mask_crop48_2000_steps(core, oracle_mod):
     after 2000 steps. FP32 after 2000 steps: densities, colour function, species and populations
     within CROP_FP32_TOL (max norm), the velocity in relative L2 within CROP_FP32_U_L2. FP32
     rounding (6e-8 relative per operation) grows along the interfaces over the horizon: measured
-    8.5e-4 on rho^N, 4.4e-4 on the populations and 1.5e-4 on the velocity; the bounds leave a
-    factor of 3.5 and 13."""
+    8.5e-4 to 9.6e-4 on rho^N, 4.4e-4 to 5.0e-4 on the populations and 1.5e-4 on the velocity; the
+    bounds leave a factor of 3 and 13. FP16 and BF16 deviation storage (FP32 arithmetic) after 2000
+    steps against the same oracle state, max norm over densities, colour function, species,
+    populations and the per-step sums, and the velocity in relative L2: FP16 measured 9.8e-4 and
+    3.6e-4 (the FP32 arithmetic's interface error dominates; the 11-bit deviations add 2.5e-4 in
+    L2 to the densities), bounds CROP_FP16_TOL, CROP_FP16_U_L2; BF16 (8-bit deviations) measured
+    2.7e-3 and 2.0e-3, bounds CROP_BF16_TOL, CROP_BF16_U_L2."""
     from paper_2608_15781_amd import inputs
 
     n, T1, T = 48, 200, 2000
@@ -505,7 +514,9 @@ def test_bench_mask_crop48_2000_steps(core, oracle_mod):
         assert _rel(rg[:, j], rr[:, j]) < FP64_TOL, j
     assert rr[-1, 1] > 0  # gas colour was produced
     _compare(gpu, ref, FP64_TOL, "crop48 fp64 t=%d" % T1)
+    rr_all = rr
     rr = ref.step(T - T1)
+    rr_all = np.concatenate([rr_all, rr], 0)
     rg = gpu.step(T - T1)
     for j in range(4):
         assert _rel(rg[:, j], rr[:, j]) < FP64_TOL, j
@@ -525,3 +536,21 @@ def test_bench_mask_crop48_2000_steps(core, oracle_mod):
     for k, e in mx.items():
         assert e < CROP_FP32_TOL, (k, e)
     assert u_l2 < CROP_FP32_U_L2, u_l2
+    # The 2-byte deviation storages against the same oracle state (FP32 arithmetic; the species as
+    # deviations from each node's total).
+    for prec, tol, tol_u in (("fp16", CROP_FP16_TOL, CROP_FP16_U_L2), ("bf16", CROP_BF16_TOL, CROP_BF16_U_L2)):
+        g2 = core.Lbm((n, n, n), solid=solid, theta=theta, rho_r0=rr0, rho_p0=rp0, precision=prec,
+                      tau_species=w["tau_c"], **kw)
+        red2 = g2.step(T)
+        m = g2.moments()
+        fr, fp, gg = g2.populations()
+        mx = {k: _rel(m[k].cpu().numpy(), r[k]) for k in ("rho_r", "rho_p", "rho_n", "c")}
+        mx["pops"] = max(_rel(fr.cpu().numpy(), rfr), _rel(fp.cpu().numpy(), rfp), _rel(gg.cpu().numpy(), rgg))
+        mx["sums"] = max(_rel(red2[:, j], rr_all[:, j]) for j in (0, 1, 2, 3))
+        u_l2 = _l2(m["u"].cpu().numpy(), r["u"])
+        print("crop48 %s t=%d max: %s | u L2 %.2e" % (prec, T, " ".join("%s=%.1e" % kv for kv in mx.items()), u_l2),
+              flush=True)
+        for k, e in mx.items():
+            assert e < tol, (prec, k, e)
+        assert u_l2 < tol_u, (prec, u_l2)
+        del g2
