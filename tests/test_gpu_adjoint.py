@@ -315,19 +315,19 @@ def test_adjoint96_crop_gradient_against_oracle_duals(core, oracle_mod):
         assert abs(a - b) < 1e-8 * abs(b) + 1e-14, (a, b)
 
 
-@pytest.mark.parametrize("prec,tol_th,tol_xi,tol_L", [("fp32", 1e-2, 1e-5, 1e-5), ("fp16", 0.15, 3e-4, 6e-5),
-                                                      ("bf16", None, 1e-2, 1e-4)])
+@pytest.mark.parametrize("prec,tol_th,tol_xi,tol_L", [("fp32", 1e-2, 1e-5, 1e-5), ("fp16", 0.15, 5e-5, 6e-5),
+                                                      ("bf16", 0.3, 5e-4, 1e-4)])
 def test_reduced_precision_adjoint_against_fp64(core, prec, tol_th, tol_xi, tol_L):
     """The adjoint in FP32 arithmetic (FP32 storage, or FP16/BF16 deviation storage whose rounding
     the adjoint takes as the identity) against the FP64 adjoint of the same problem: 24^3 porous
-    mask, 100 steps, checkpoint 10. FP32 and the integral quantities: bounds about 6x the errors
-    measured on this case (FP32: dL/dtheta 1.7e-3 relative L2, dL/dxi 1.3e-6, L 1.5e-6; FP16:
-    dL/dxi 1.0e-4 at most, L 1.2e-5; BF16: dL/dxi 9.1e-4, L 2.7e-5). The FP16 per-node contact-angle
-    gradient is set by a few wetting nodes whose realignment branch or normal guard falls
-    differently under the storage rounding: the same case measured 4.3e-3 and 5.5e-2 in builds
-    that differ only in where multiply-adds are contracted, and a 48^3 case 8.9e-2, so it is
-    bounded at 0.15. BF16's 8-bit deviations leave that gradient without a usable bound (about
-    0.4-0.5 relative): only the integral quantities are checked there."""
+    mask, 100 steps, checkpoint 10. Measured on this case: FP32 dL/dtheta 1.7e-4 (relative L2),
+    dL/dxi 1.2e-6, L 1.6e-6; FP16 1.5e-3, 6.2e-6, 1.0e-5; BF16 3.8e-2, 7.0e-5, 1.2e-5. The
+    integral quantities are bounded at 6-8x those. The per-node contact-angle gradient is set by a
+    few wetting nodes whose realignment branch falls differently under the rounding (half of the
+    squared error sits on ten nodes in every mode), and builds that differ only in where
+    multiply-adds are contracted have measured it up to 20x apart (FP32 3.5e-3 in one such build),
+    so it is bounded more loosely: 1e-2, 0.15 and 0.3; a 48^3 case over 200 steps measures 5.4e-3,
+    4.8e-3 and 0.28."""
     from paper_2608_15781_amd import autograd as ag
 
     n, T, seed = 24, 100, 43
