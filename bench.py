@@ -221,7 +221,34 @@ def step_roofline(mflups, kern, nfluid, precision, workload, copy_gbs):
            "kernel_ms": {k: round(v, 5) for k, v in kern.items()}}
     if traffic is not None:
         out["traffic_bytes_per_fluid_update"] = round(traffic / nfluid, 1)
+    per = {}
+    for k, ms in kern.items():
+        alg = kernel_alg_bytes(precision).get(k)
+        e = {"ms": round(ms, 5)}
+        if alg is not None:
+            gbs = alg * nfluid / (ms * 1e-3) / 1e9
+            e.update(alg_bytes_per_fluid_node=alg, achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+        t = measured_step_traffic(workload, precision, ["lbm::k_%s<" % k])
+        if t is not None:
+            e.update(traffic_bytes_per_fluid_node=round(t / nfluid, 1),
+                     traffic_gbs=round(t / (ms * 1e-3) / 1e9, 1))
+        per[k] = e
+    out["per_kernel"] = per
     return out
+
+
+def kernel_alg_bytes(precision):
+    """Algorithmic bytes per fluid node of the colour, normal and collide passes (each array element
+    they need moved once; s = storage bytes, r = arithmetic bytes): colour pulls 19 colour-blind
+    populations and the 4 colour scalars and writes rho^N; normal reads rho^N and the wetting
+    data and writes (n*, |G|); collide pulls and writes the 26 populations and 4 scalars and reads
+    rho^N and the normals (plus the species totals with 2-byte storage). The extrapolation pass
+    works on solid nodes and has no per-fluid-node figure."""
+    s = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[precision]
+    r = 8 if precision == "fp64" else 4
+    extra = 2 * r if s == 2 else 0
+    return {"colour": 19 * s + 4 * r + 4 + r, "normal": r + 4 + 4 * r + 4 * r,
+            "collide": 26 * s + r + 4 * r + 4 + 26 * s + 4 * r + extra}
 
 
 def main():
