@@ -52,7 +52,8 @@ constexpr int kXcd = 8;
 
 
 // Per-node 4-vectors (colour scalars a, v; realigned normal and |G|; wetting data) are stored
-// together (16 or 32 bytes per node) so that one load brings all four.
+// together (16 or 32 bytes per node) so that one load brings all four: a gather's cost follows
+// the cache lines it touches, so loading a subset of the four costs about as much as all four.
 template <class R> struct V4;
 template <> struct V4<float> { using T = float4; };
 template <> struct V4<double> { using T = double4; };
@@ -422,8 +423,9 @@ __global__ __launch_bounds__(kBlock) void k_finish_reduce(const double* partials
 
 // ---------------------------------------------------------------------------------------------
 // colour: rho^N = (rho^r - rho^p)/rho^m from the pulled populations. The pull-source ids come
-// from pull_sources (most of them derived from a neighbour's rank); the pass then fits in 60
-// VGPRs and eight waves per SIMD, and is bound by its gathers, not by its bytes.
+// from pull_sources (most of them derived from a neighbour's rank) and the sources' colour
+// scalars from row_shared (one gather per row triple); the pass is bound by its gathers' address
+// and cache-line work, not by its bytes (102 VGPRs, four waves per SIMD).
 // ---------------------------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_colour(StepArgs<P> A) {
